@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the local p-multigrid patch-smoother solver on one MI355X.
+
+Workload: 3D Poisson on the unit cube, 32^3 hexahedra, Q4 Gauss-Lobatto elements
+(2,146,689 nodes), homogeneous Dirichlet, seeded uniform[-1,1] right-hand side; h-multigrid
+V(1,1) (levels 2..32 cells) with the vertex-patch smoother whose local solver is one half
+V-cycle over the p-levels 4 -> 3 -> 1, inside flexible CG, all FP64.
+
+One step = one solve from x = 0 to |b - A x| <= 1e-8 |b| (apply, smoother color passes
+with the fused local p-multigrid, residuals, transfers, coarse solve, dot products: the
+whole path).  value = nodes x V-cycles / time (DoF/s per V-cycle).  The same solve with
+FP32 multigrid inside the FP64 CG is timed alongside, and the finest-level smoother kernel
+(the dominant kernel) is timed with HIP events on the launch stream for the roofline.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_events(fn, reps, torch):
+    """Mean milliseconds per call of fn() between HIP events on the current stream."""
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(dim, n, p, seed, budget_s=12.0):
+    """The oracle (NumPy/SciPy, one thread) timed on V-cycles of a reduced mesh."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.solver import MultigridProblem
+    from paper_2512_02577_amd.inputs import rhs_vector
+
+    with threadpool_limits(1):
+        pb = MultigridProblem(dim, n, p)
+        r = rhs_vector(dim, n, p, seed)
+        pb.vcycle(r)  # builds the patch caches (setup)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < budget_s or k < 3:
+            pb.vcycle(r)
+            k += 1
+        t = time.perf_counter() - t0
+    return pb.N * k / t, k, t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2512_02577_amd import perfmodel, pmg
+    from paper_2512_02577_amd.inputs import rhs_vector
+
+    dim, n, p, seed = 3, 32, 4, 2
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    log(f"bench: setup 3D n={n} Q{p}")
+    pr = pmg.make_problem(dim, n, p)
+    N = pr.n_nodes[-1]
+    b = torch.as_tensor(rhs_vector(dim, n, p, seed), dtype=torch.float64, device=dev)
+    x = torch.empty_like(b)
+
+    def run_solves(prec, k):
+        its = []
+        for _ in range(k):
+            info = pmg.solve(pr, b, x, prec)
+            its.append(info.iterations)
+        return its
+
+    log("bench: warmup")
+    run_solves(pmg.FP64, args.warmup)
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} FP64 solves")
+    t0 = time.perf_counter()
+    its = run_solves(pmg.FP64, args.steps)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    relres64 = pmg.solve(pr, b, x, pmg.FP64).rel_residual
+    x64 = x.clone()
+
+    log("bench: FP32-MG solves")
+    run_solves(pmg.FP32, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its32 = run_solves(pmg.FP32, args.steps)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    info32 = pmg.solve(pr, b, x, pmg.FP32)
+    diff32 = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+
+    # per-call rates with HIP events on torch's current stream (the launch stream)
+    log("bench: per-call timings")
+    L = pr.finest
+    u = torch.as_tensor(np.random.default_rng(3).uniform(-1, 1, N), dtype=torch.float64, device=dev)
+    v = torch.empty_like(u)
+    z = torch.empty_like(u)
+    reps = args.kernel_reps
+    t_apply = time_events(lambda: pmg.apply_operator(pr, L, u, v), reps, torch)
+    u_s = u.clone()
+    t_smooth = time_events(lambda: pmg.smooth(pr, L, u_s, b, 1), reps, torch)
+    t_vc = time_events(lambda: pmg.vcycle(pr, b, z, pmg.FP64), max(5, reps // 5), torch)
+    t_vc32 = time_events(lambda: pmg.vcycle(pr, b, z, pmg.FP32), max(5, reps // 5), torch)
+    u32 = u.float()
+    b32 = b.float()
+    t_smooth32 = time_events(lambda: pmg.smooth(pr, L, u32, b32, 1), reps, torch)
+
+    # dominant kernel: the finest-level smoother color kernel (8 launches per application)
+    ncol = 2 ** dim
+    bytes_launches = sum(perfmodel.smooth_launch_bytes(dim, n, p, c) for c in range(ncol))
+    patches = sum(perfmodel.smooth_launch_patches(dim, n, c) for c in range(ncol))
+    flops = patches * perfmodel.patch_flops(dim, p, pr.degrees)
+    t_launch = t_smooth / ncol * 1e-3
+    ach_gbs = bytes_launches / ncol / t_launch / 1e9
+    ach_tf = flops / ncol / t_launch / 1e12
+    ai = flops / bytes_launches
+    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    bound = "hbm" if ai < ridge else "alu"
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach_gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(ach_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach_tf / FP64_PEAK_TFLOPS, 4)}
+    roof.update({"traffic": None, "kernel": "k_smooth<3,double,4,{1,3,4}> (finest level, one color launch)",
+                 "avg_launch_us": round(t_launch * 1e6, 2), "bytes_per_launch": bytes_launches // ncol,
+                 "flops_per_launch": flops // ncol, "flop_per_byte": round(ai, 2),
+                 "achieved_tflops": round(ach_tf, 3), "achieved_gbs": round(ach_gbs, 1)})
+
+    out = {
+        "metric": "DoF/s per V-cycle + time-to-1e-8 residual, FP64 vs FP32-MG, one MI355X",
+        "value": N * sum(its) / t64,
+        "unit": "DoF/s per V-cycle",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t64 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded uniform[-1,1] right-hand side)",
+        "config": {"workload": "3D Poisson, unit cube, 32^3 hexes, Q4 GLL, Dirichlet, FP64 h-MG(V(1,1), vertex-patch "
+                               "smoother, local half V-cycle p=4->3->1) in flexible CG to rtol 1e-8",
+                   "n_dofs": N, "n_cells": n ** dim, "degree": p, "parallelism": "single GPU"},
+        "time_to_solution_s": {"fp64": t64 / args.steps, "fp32_mg": t32 / args.steps},
+        "iterations": {"fp64": its[-1], "fp32_mg": its32[-1]},
+        "rel_residual": {"fp64": relres64, "fp32_mg": info32.rel_residual},
+        "fp32_mg_solution_rel_diff_vs_fp64": diff32,
+        "dof_per_s": {"apply_fp64": N / (t_apply * 1e-3), "smooth_fp64": N / (t_smooth * 1e-3),
+                      "smooth_fp32": N / (t_smooth32 * 1e-3), "vcycle_fp64": N / (t_vc * 1e-3),
+                      "vcycle_fp32": N / (t_vc32 * 1e-3)},
+        "ms": {"apply_fp64": t_apply, "smooth_fp64": t_smooth, "smooth_fp32": t_smooth32, "vcycle_fp64": t_vc,
+               "vcycle_fp32": t_vc32},
+        "smooth_over_apply": t_smooth / t_apply,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (8^3 cells, Q4, V-cycles, one thread)")
+        rate, k, t = cpu_baseline(3, 8, 4, seed)
+        out["cpu_baseline"] = {"value": rate, "unit": "DoF/s per V-cycle", "cores": 1, "kind": "oracle",
+                               "sample": f"{k} oracle V-cycles on 8^3 cells Q4 (35,937 DoFs), setup excluded, "
+                                         f"{t:.1f} s; host {platform.processor() or platform.machine()}, "
+                                         f"{os.cpu_count()} logical CPUs"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

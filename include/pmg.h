@@ -1,0 +1,194 @@
+/*
+ * pmg.h -- C interface of the MI355X (gfx950) local p-multigrid vertex-patch smoother
+ * library (libpmg.so).
+ *
+ * The library solves the homogeneous Dirichlet problem A u = b of the Q_p Laplacian
+ * -div(grad u) = f on a structured mesh of the unit square or cube (paper Sec. 2,
+ * eq. bilinear-form and eq. matrix) with an h-multigrid preconditioned flexible CG whose
+ * smoother is the multiplicative vertex-patch smoother (Sec. 2.1, Alg. 1) with a local
+ * p-multigrid patch solver (Sec. 2.2, Alg. 2 and Alg. 3).  Every operator is applied
+ * matrix-free by sum factorization in hand-written HIP kernels.
+ *
+ * Conventions shared by all entry points
+ *   - Vectors are caller-owned device pointers (float64 for PMG_FP64, float32 for
+ *     PMG_FP32) of length N(l) = (p*n_l + 1)^dim on h-level l: one entry per node of the
+ *     degree-p node grid, boundary nodes included, lexicographic with x fastest: node
+ *     (i, j, k) has index i + m*(j + m*k), m = p*n_l + 1.
+ *   - Cells are numbered cx + n*(cy + n*cz); cell-local nodes a + (p+1)*(b + (p+1)*e);
+ *     the patch of interior vertex (vx, vy, vz), 1 <= v <= n-1, has index
+ *     (vx-1) + (n-1)*((vy-1) + (n-1)*(vz-1)); its closure is the node box
+ *     p(v-1) <= i <= p(v+1) per direction, its interior the open box; both are listed x
+ *     fastest.  Patch colors are sum_k (v_k mod 2) 2^k (2^dim colors; two patches of one
+ *     color never have one's interior inside the other's closure, Sec. 4.4).
+ *   - h-levels are numbered 0 (coarsest) .. n_hlevels-1 (finest); p-levels 0 (degree 1)
+ *     .. n_plevels-1 (degree p).
+ *   - Dirichlet rows are identity rows: (A u)_i = u_i on boundary nodes and interior rows
+ *     do not see boundary values.
+ *   - Streams are hipStream_t passed as void*; NULL is the default stream.  Device entry
+ *     points enqueue work and return without synchronizing, except pmg_solve.
+ *   - Every function returns PMG_OK (0) or a negative status; pmg_last_error() gives a
+ *     thread-local message.  Arguments are validated before anything is enqueued, so a
+ *     failed call leaves its outputs untouched.  No C++ exception crosses the interface.
+ *   - Handles are library-owned; a problem may be used by one stream at a time.
+ *     Device buffers are allocated in pmg_device_init only; later calls allocate
+ *     nothing.
+ */
+#ifndef PMG_H
+#define PMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PMG_OK = 0,
+  PMG_ERR_INVALID_ARG = -1,
+  PMG_ERR_UNSUPPORTED = -2,
+  PMG_ERR_OUT_OF_MEMORY = -3,
+  PMG_ERR_DEVICE = -4,
+  PMG_ERR_NOT_CONVERGED = -5,
+  PMG_ERR_BREAKDOWN = -6,
+  PMG_ERR_STATE = -7
+};
+
+/* Arithmetic of a call: vectors and computation in float64 or float32. */
+enum { PMG_FP64 = 0, PMG_FP32 = 1 };
+
+/* Local patch solver (Sec. 2.2): one half V-cycle (no post-smoothing, Sec. 2.2.1) or a
+ * full V-cycle per Richardson step. */
+enum { PMG_LOCAL_HALF_V = 0, PMG_LOCAL_FULL_V = 1 };
+
+typedef struct {
+  int local_solver; /* PMG_LOCAL_HALF_V (default) or PMG_LOCAL_FULL_V                  */
+  int n_local_iter; /* Richardson steps of LocalSolve (Alg. 2), >= 1; default 1          */
+  int n_pre;        /* smoother applications before the coarse correction, default 1     */
+  int n_post;       /* smoother applications after it (descending colors), default 1     */
+  int max_iter;     /* outer flexible-CG iteration limit, default 200                    */
+  double rtol;      /* outer stop: |b - A x|_2 <= rtol |b|_2, default 1e-8               */
+  int n_omega;      /* 0: library damping; else the number of valid entries in omega     */
+  double omega[8];  /* Jacobi damping per p-level, coarsest first (entry 0 is unused)    */
+} pmg_config;
+
+typedef struct {
+  int iterations;      /* outer iterations performed                                  */
+  double rel_residual; /* final |b - A x|_2 / |b|_2 (recursively updated residual)    */
+  double seconds;      /* wall time of the call                                       */
+  int status;          /* same value as the return code                               */
+} pmg_solve_info;
+
+typedef struct pmg_mesh pmg_mesh;
+typedef struct pmg_problem pmg_problem;
+
+/* Thread-local text of the last error. */
+const char *pmg_last_error(void);
+
+/* Fills cfg with the defaults listed in pmg_config. */
+void pmg_default_config(pmg_config *cfg);
+
+/* Mesh hierarchy M_0 ... M_L of nested structured meshes (Sec. 2).
+ *   dim       2 or 3.
+ *   n         cells per direction on the finest mesh, 2 <= n <= 1024.
+ *   n_hlevels number of h-levels, or 0: halve n while it is even and above 3.
+ *   vertices  NULL for the uniform Cartesian unit box.  Otherwise host array of
+ *             (n+1)^dim * dim doubles (vertex-major, x fastest) of a distorted mesh; the
+ *             general-geometry path is not built yet and such calls return
+ *             PMG_ERR_UNSUPPORTED.
+ * The mesh owns a copy of everything it needs; *out is set on success only. */
+int pmg_setup_mesh(int dim, int n, int n_hlevels, const double *vertices, pmg_mesh **out);
+
+/* Dimension and number of h-levels (either may be NULL); if n_cells is not NULL it
+ * receives the cells per direction of each level, coarsest first (host array of
+ * n_hlevels entries). */
+int pmg_mesh_levels(const pmg_mesh *m, int *dim, int *n_hlevels, int32_t *n_cells);
+
+void pmg_destroy_mesh(pmg_mesh *m);
+
+/* Degree-p discretization, patch maps and p-hierarchy on every h-level (host only).
+ *   degree    1 <= p <= 8.
+ *   p_levels  NULL: the paper's hierarchy (Sec. 2.2): 1, 3, 7, ... below p, then p.
+ *             Else n_plevels ascending degrees starting at 1 and ending at p; supported
+ *             lists are the paper's and 1, 2, ..., p for p <= 4.
+ *   cfg       NULL for pmg_default_config().
+ * The mesh may be destroyed afterwards. */
+int pmg_setup_dofmap(const pmg_mesh *m, int degree, const int32_t *p_levels, int n_plevels,
+                     const pmg_config *cfg, pmg_problem **out);
+
+/* Sizes (every output may be NULL): dim, counts of h- and p-levels, n_cells[l] = n_l,
+ * n_nodes[l] = N(l) and n_patches[l] = (n_l - 1)^dim per h-level (host arrays of
+ * n_hlevels entries), degrees of the p-levels and the Jacobi damping actually used per
+ * p-level (n_plevels entries). */
+int pmg_problem_sizes(const pmg_problem *pr, int *dim, int *n_hlevels, int *n_plevels, int32_t *n_cells,
+                      int64_t *n_nodes, int64_t *n_patches, int32_t *degrees, double *omega);
+
+/* Index maps of h-level `hlevel` at the degree of p-level `plevel`, computed by the same
+ * index arithmetic the kernels use, into caller-owned host arrays (any may be NULL):
+ *   cell_dofs      n_l^dim x (q+1)^dim
+ *   patch_interior (n_l-1)^dim x (2q-1)^dim
+ *   patch_closure  (n_l-1)^dim x (2q+1)^dim
+ *   patch_color    (n_l-1)^dim                                                   */
+int pmg_export_maps(const pmg_problem *pr, int hlevel, int plevel, int32_t *cell_dofs,
+                    int32_t *patch_interior, int32_t *patch_closure, uint8_t *patch_color);
+
+/* Uploads the operator tables and allocates every device workspace on the current HIP
+ * device.  Must be called once before any entry point below. */
+int pmg_device_init(pmg_problem *pr);
+
+/* v = A_l u on h-level `hlevel` (eq. matrix): matrix-free sum-factorized apply of the
+ * degree-p operator; boundary rows copy u.  u and v must not overlap. */
+int pmg_apply_operator(pmg_problem *pr, int hlevel, int prec, const void *u, void *v, void *stream);
+
+/* r = b - A_l u on h-level `hlevel` (boundary rows: b_i - u_i).  r must not overlap u, b. */
+int pmg_residual(pmg_problem *pr, int hlevel, int prec, const void *b, const void *u, void *r,
+                 void *stream);
+
+/* One application of the multiplicative vertex-patch smoother (Alg. 1) on h-level
+ * `hlevel`, updating u in place: colors ascending (color_dir = +1) or descending (-1),
+ * every patch of a color in parallel.  For each patch: gather the closure of u, form the
+ * patch residual r_j = Pi_j b - Pi_j Abar_j ubar_j, run LocalSolve (Alg. 2 with Alg. 3
+ * cycles over the p-levels, damped Jacobi with precomputed inverse diagonals, exact 1x1
+ * solve at degree 1) and add d_j to the patch interior of u.  Requires hlevel >= 1 and
+ * n_l >= 2. */
+int pmg_smooth(pmg_problem *pr, int hlevel, int prec, int color_dir, void *u, const void *b,
+               void *stream);
+
+/* LocalSolve (Alg. 2) alone for a contiguous range of patches of h-level `hlevel`:
+ * r and d hold n_patches blocks of (2p-1)^dim patch-interior values (x fastest), block i
+ * belonging to patch first_patch + i. */
+int pmg_local_solve(pmg_problem *pr, int hlevel, int prec, int first_patch, int n_patches,
+                    const void *r, void *d, void *stream);
+
+/* Restriction by the transposed embedding (Sec. 2): coarse = R fine, fine on h-level
+ * `hlevel` >= 1, coarse on hlevel-1; coarse boundary entries are set to zero. */
+int pmg_restrict(pmg_problem *pr, int hlevel, int prec, const void *fine, void *coarse, void *stream);
+
+/* fine += P coarse (embedding, Sec. 2); fine boundary entries are left unchanged. */
+int pmg_prolongate_add(pmg_problem *pr, int hlevel, int prec, const void *coarse, void *fine,
+                       void *stream);
+
+/* Exact solve on the coarsest mesh: z = A_0^{-1} r (interior, computed in float64 for
+ * either precision), z_i = r_i on boundary nodes. */
+int pmg_coarse_solve(pmg_problem *pr, int prec, const void *r, void *z, void *stream);
+
+/* One h-multigrid V(n_pre, n_post) cycle from a zero guess on the finest level:
+ * z = V(r).  r and z are float64; mg_prec selects the arithmetic of the whole cycle
+ * (PMG_FP32: r is rounded to float32 on entry, z widened on exit, the coarse solve
+ * stays float64). */
+int pmg_vcycle(pmg_problem *pr, int mg_prec, const double *r, double *z, void *stream);
+
+/* Flexible CG (float64 vectors, dot products and updates) preconditioned by pmg_vcycle
+ * in mg_prec, until |b - A x|_2 <= rtol |b|_2 or max_iter.  Synchronizes the stream once
+ * per iteration for the convergence test.  Returns PMG_ERR_NOT_CONVERGED or
+ * PMG_ERR_BREAKDOWN (a non-positive or non-finite curvature) with info filled; x then
+ * holds the last iterate. */
+int pmg_solve(pmg_problem *pr, int mg_prec, const double *b, double *x, int x_is_initial_guess,
+              pmg_solve_info *info, void *stream);
+
+void pmg_destroy_problem(pmg_problem *pr);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMG_H */

@@ -134,3 +134,47 @@ def quadrature_points(mesh: StructuredMesh, p: int, nq: int | None = None) -> np
     """Physical Gauss points of every cell, (n_cells, nq^dim, dim), x fastest."""
     pts, _, _, _ = reference_tables(mesh.dim, p, nq or p + 1)
     return np.stack([multilinear_map(mesh.cell_corners(c), pts)[0] for c in range(mesh.n_cells())])
+
+
+def apply_rows(mesh: StructuredMesh, p: int, u: np.ndarray, rows: np.ndarray, coef=None) -> np.ndarray:
+    """(A u)_i for selected global rows i without assembling A: the sum over the cells
+    that contain node i of (element matrix row) . (element values of u), with the
+    Dirichlet convention (identity rows on the boundary, boundary values of u ignored)."""
+    dim, n = mesh.dim, mesh.n
+    m = p * n + 1
+    bnd = boundary_nodes(dim, n, p)
+    out = np.zeros(len(rows))
+    cache = {}
+    for r_i, g in enumerate(np.asarray(rows)):
+        if bnd[g]:
+            out[r_i] = u[g]
+            continue
+        idx = [(g // m**a) % m for a in range(dim)]
+        cands = []
+        for a in range(dim):
+            c = idx[a] // p
+            cs = {min(c, n - 1)}
+            if idx[a] % p == 0 and idx[a] > 0:
+                cs.add(idx[a] // p - 1)
+            cands.append(sorted(x for x in cs if 0 <= x < n))
+        total = 0.0
+        for cell in np.array(np.meshgrid(*cands, indexing="ij")).reshape(dim, -1).T:
+            c = int(sum(cell[a] * n**a for a in range(dim)))
+            loc = [idx[a] - p * cell[a] for a in range(dim)]
+            if any(l < 0 or l > p for l in loc):
+                continue
+            li = int(sum(loc[a] * (p + 1) ** a for a in range(dim)))
+            corners = mesh.cell_corners(c)
+            if coef is None:
+                key = np.round(corners - corners[0], 13).tobytes()
+                if key not in cache:
+                    cache[key] = element_stiffness(p, corners)
+                Ae = cache[key]
+            else:
+                Ae = element_stiffness(p, corners, coef)
+            dofs = np.array([sum((p * cell[a] + ((e // (p + 1) ** a) % (p + 1))) * m**a for a in range(dim))
+                             for e in range((p + 1) ** dim)])
+            ue = np.where(bnd[dofs], 0.0, u[dofs])
+            total += Ae[li] @ ue
+        out[r_i] = total
+    return out

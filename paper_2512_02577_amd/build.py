@@ -1,0 +1,89 @@
+"""Builds the HIP library libpmg.so (gfx950) and the CPU emulation library of its kernel
+bodies, in-tree, next to this file.
+
+    python -m paper_2512_02577_amd.build          # both libraries
+    python -m paper_2512_02577_amd.build --asan   # also the bounds-checked emulation runner
+
+Every call compiles from scratch; objects go to paper_2512_02577_amd/_build/.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libpmg.so")
+EMU = os.path.join(PKG, "libpmg_hostemu.so")
+
+HIP_SOURCES = ["kernels_3d_f64.hip", "kernels_3d_f32.hip", "kernels_2d_f64.hip", "kernels_2d_f32.hip",
+               "blas.hip", "capi.cpp", "kernels_dispatch.cpp", "host_tables.cpp"]
+HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+               # no packed FP32 instructions anywhere in the device code
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+
+
+def _hipcc() -> str:
+    for cand in ("/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def _run(cmd: list[str]) -> None:
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
+    if res.returncode != 0:
+        raise RuntimeError(f"command failed ({res.returncode}): {' '.join(cmd)}\n{err}")
+
+
+def build_hip(jobs: int = 8) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    hipcc = _hipcc()
+    cmds, objs = [], []
+    for src in HIP_SOURCES:
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        lang = ["-x", "hip"] if src.endswith(".cpp") and src != "host_tables.cpp" else []
+        cmds.append([hipcc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(cmds)))) as ex:
+        list(ex.map(_run, cmds))
+    tmp = LIB + ".tmp"
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def build_emulation(asan: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = [os.path.join(CSRC, "hostemu.cpp"), os.path.join(CSRC, "host_tables.cpp")]
+    tmp = EMU + ".tmp"
+    _run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I" + CSRC, *srcs, "-o", tmp])
+    os.replace(tmp, EMU)
+    if asan:
+        exe = os.path.join(BUILD, "hostemu_asan")
+        _run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+              "-I" + CSRC, os.path.join(CSRC, "hostemu_check.cpp"), *srcs, "-o", exe])
+        return exe
+    return EMU
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--asan", action="store_true")
+    ap.add_argument("--jobs", type=int, default=8)
+    args = ap.parse_args(argv)
+    print(build_hip(args.jobs))
+    print(build_emulation(args.asan))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

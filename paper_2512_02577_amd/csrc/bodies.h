@@ -1,0 +1,453 @@
+// Kernel bodies of the p-multigrid patch smoother library.
+//
+// Each body is written for one workgroup (threads tid = 0..NT-1, LDS arena `lds`) and
+// is __host__ __device__, so that the HIP kernels run it on gfx950 and a CPU build runs
+// it with NT = 1 for index and bounds checking.
+//
+// Discretization on a Cartesian h-level with cell size h (paper Sec. 2 and Sec. 3): the
+// operator is c * sum_k K_k (x) M_others with c = h^(dim-2) and K, M the 1D reference
+// stiffness and mass matrices of the degree-p Gauss-Lobatto Lagrange basis integrated by
+// the (p+1)-point Gauss rule.  All 1D tables come from host_tables.cpp.
+#pragma once
+
+#include "sumfac.h"
+
+namespace pmg {
+
+template <typename T>
+struct DevTabs {
+  const T *Kp[4], *Mp[4], *invD[4], *Tp[4], *TpT[4];  // per p-level, coarsest first
+  const T *Kr, *Mr;                                   // patch residual (degree p)
+  const T *Kt, *Mt;                                   // apply tile (degree p)
+  const T *W1, *Wr;                                   // h-embedding
+};
+
+// Workgroup -> work item mapping that keeps consecutive items on one XCD: the hardware
+// hands workgroups round-robin to the 8 XCDs, each with its own L2, so item ranges are
+// split into 8 contiguous chunks and workgroup b takes item (b / 8) of chunk (b % 8).
+PMG_INLINE int xcd_remap(int b, int G) {
+  const int per = G / 8, rem = G % 8, x = b % 8, loc = b / 8;
+  return x * per + (x < rem ? x : rem) + loc;
+}
+
+// ---------------------------------------------------------------------------------------
+// Vertex-patch smoother (Alg. 1 body for one patch, Alg. 2 local solve, Alg. 3 p-cycle).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct SmoothArgs {
+  DevTabs<T> tb;
+  T c, cinv;         // h^(d-2) and its inverse
+  int n;             // cells per direction of this h-level
+  int first[3];      // first patch vertex coordinate of the color per axis (1 or 2)
+  int cnt[3];        // patches of the color per axis
+  int n_patch;       // cnt[0]*cnt[1]*cnt[2]
+  int full;          // full V-cycle (post-smoothing) instead of the half V-cycle
+  int n_iter;        // Richardson steps of LocalSolve
+  T *u;              // solution, updated on patch interiors
+  const T *b;        // right-hand side
+  // local-solve-only mode (pmg_local_solve): r/d blocks per patch, patch index offset
+  const T *r_blocks;
+  T *d_blocks;
+  int first_patch;
+};
+
+template <int... Qs>
+struct Degrees {
+  static constexpr int L = sizeof...(Qs);
+  static constexpr int q[L] = {Qs...};
+};
+
+template <int DIM, typename T, int NT, int P, class H>
+struct PatchBody {
+  static constexpr int L = H::L;
+  static_assert(H::q[L - 1] == P, "top p-level must be the degree");
+  static_assert(H::q[0] == 1, "coarsest p-level must be degree 1");
+  static constexpr int N = 2 * P + 1, n = 2 * P - 1;
+  static constexpr int Nd = ipow(N, DIM), nd = ipow(n, DIM);
+  static constexpr int qd(int l) { return H::q[l]; }
+  static constexpr int nl(int l) { return 2 * H::q[l] - 1; }
+  static constexpr int ndl(int l) { return ipow(2 * H::q[l] - 1, DIM); }
+
+  // ---- LDS layout ----
+  // phase R (patch residual):  r | ucl (later stage-2 output) | stage-1 output
+  // phase S (local solve):     r | d | c | lower-level r_l, d_l | scratch X | scratch Y
+  // Scratch roles: a level vmult writes its stage-1 pair into X and stage-2 pair into Y;
+  // the result `res` goes to X in 3D (stage-1 pair is dead by then) and to Y in 2D; the
+  // transfer temporaries use Y in 3D and X in 2D.
+  using RS = LapScratch<DIM, N, n>;
+  static constexpr int R0 = cmax(Nd, RS::cg);
+  static constexpr int off_r = 0;  // patch residual, then running Richardson residual
+  static constexpr int off_ucl = nd;
+  static constexpr int off_abR = nd + R0;
+  static constexpr int phaseR_end = nd + R0 + RS::ab;
+  static constexpr int off_d = nd;
+  static constexpr int off_cc = 2 * nd;
+  static constexpr int lower_size(int l) { return l < 0 ? 0 : 2 * ndl(l) + lower_size(l - 1); }
+  static constexpr int off_lr(int l) { return 3 * nd + (l == 0 ? 0 : lower_size(l - 1)); }
+  static constexpr int off_ld(int l) { return off_lr(l) + ndl(l); }
+  static constexpr int level_x(int l) {  // scratch X need of level l (and its transfers)
+    return DIM == 3 ? lap_ab(DIM, nl(l), nl(l))
+                    : cmax(lap_ab(DIM, nl(l), nl(l)),
+                           l > 0 ? cmax(kron_t1(DIM, nl(l), nl(l - 1)), kron_t1(DIM, nl(l - 1), nl(l))) : 0);
+  }
+  static constexpr int level_y(int l) {
+    return DIM == 3 ? cmax(lap_cg(DIM, nl(l), nl(l)),
+                           l > 0 ? cmax(kron_t1(DIM, nl(l), nl(l - 1)) + kron_t2(DIM, nl(l), nl(l - 1)),
+                                        kron_t1(DIM, nl(l - 1), nl(l)) + kron_t2(DIM, nl(l - 1), nl(l)))
+                                 : 0)
+                    : ndl(l);
+  }
+  static constexpr int scr_x() {
+    int s = 0;
+    for (int l = 0; l < L; ++l) s = cmax(s, level_x(l));
+    return s;
+  }
+  static constexpr int scr_y() {
+    int s = 0;
+    for (int l = 0; l < L; ++l) s = cmax(s, level_y(l));
+    return s;
+  }
+  static constexpr int off_X = 3 * nd + lower_size(L - 2);
+  static constexpr int off_Y = off_X + scr_x();
+  static constexpr int size = cmax(phaseR_end, off_Y + scr_y());
+  static constexpr int off_res = DIM == 3 ? off_X : off_Y;
+  static constexpr int off_t1 = DIM == 3 ? off_Y : off_X;
+
+  // res = r - c A_l d on p-level l (interior patch operator)
+  template <int l>
+  PMG_INLINE static void vmult_residual(int tid, T *lds, const DevTabs<T> &tb, T c, const T *d, const T *r,
+                                        T *res) {
+    laplace_sf<DIM, PatInterior<qd(l)>, NT>(tid, d, res, r, c, tb.Kp[l], tb.Mp[l], lds + off_X, lds + off_Y);
+  }
+
+  // Alg. 3 on p-level l: d = V(l, r), zero initial guess.
+  template <int l>
+  PMG_INLINE static void cycle(int tid, T *lds, const DevTabs<T> &tb, T c, T cinv, const T *r, T *d,
+                               bool full) {
+    if constexpr (l == 0) {
+      if (tid == 0) d[0] = cinv * tb.invD[0][0] * r[0];  // exact 1x1 solve
+      PMG_SYNC();
+    } else {
+      constexpr int q = qd(l), qc = qd(l - 1), ndq = ndl(l);
+      constexpr int t1size = DIM == 3 ? cmax(kron_t1(DIM, nl(l), nl(l - 1)), kron_t1(DIM, nl(l - 1), nl(l))) : 0;
+      const T *__restrict__ invD = tb.invD[l];
+      for (int e = tid; e < ndq; e += NT) d[e] = cinv * invD[e] * r[e];  // pre-smoothing
+      PMG_SYNC();
+      T *res = lds + off_res;
+      vmult_residual<l>(tid, lds, tb, c, d, r, res);  // res = r - A d
+      PMG_SYNC();
+      T *rc = lds + off_lr(l - 1), *dc = lds + off_ld(l - 1);
+      T *t1 = lds + off_t1, *t2 = t1 + t1size;
+      kron_all<DIM, PatRestrict<q, qc>, NT, false>(tid, res, rc, tb.TpT[l], t1, t2);
+      PMG_SYNC();
+      cycle<l - 1>(tid, lds, tb, c, cinv, rc, dc, full);
+      kron_all<DIM, PatProlong<q, qc>, NT, true>(tid, dc, d, tb.Tp[l], t1, t2);  // d += P e
+      PMG_SYNC();
+      if (full) {  // post-smoothing
+        vmult_residual<l>(tid, lds, tb, c, d, r, res);
+        PMG_SYNC();
+        for (int e = tid; e < ndq; e += NT) d[e] += cinv * invD[e] * res[e];
+        PMG_SYNC();
+      }
+    }
+  }
+
+  // Alg. 2: d = LocalSolve(r) on the top level (r at off_r, d at off_d).  Later Richardson
+  // steps keep a running residual r <- r - A c, equal to r_0 - A d.
+  PMG_INLINE static void local_solve(int tid, T *lds, const SmoothArgs<T> &a) {
+    T *r = lds + off_r, *d = lds + off_d, *cc = lds + off_cc;
+    const bool full = a.full != 0;
+    cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, full);
+    for (int it = 1; it < a.n_iter; ++it) {
+      vmult_residual<L - 1>(tid, lds, a.tb, a.c, it == 1 ? d : cc, r, r);
+      PMG_SYNC();
+      cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, cc, full);
+      for (int e = tid; e < nd; e += NT) d[e] += cc[e];
+      PMG_SYNC();
+    }
+  }
+
+  PMG_INLINE static void decode(int idx, int k[3]) {
+    k[0] = idx % n;
+    k[1] = (idx / n) % n;
+    k[2] = DIM == 3 ? idx / (n * n) : 0;
+  }
+
+  // One patch of one color: gather, residual, LocalSolve, scatter (Alg. 1 body).
+  PMG_INLINE static void smooth_patch(int tid, int blk, T *lds, const SmoothArgs<T> &a) {
+    const int pidx = xcd_remap(blk, a.n_patch);
+    int v[3];
+    v[0] = a.first[0] + 2 * (pidx % a.cnt[0]);
+    v[1] = a.first[1] + 2 * ((pidx / a.cnt[0]) % a.cnt[1]);
+    v[2] = DIM == 3 ? a.first[2] + 2 * (pidx / (a.cnt[0] * a.cnt[1])) : 0;
+    const int m = P * a.n + 1;
+    const int g0[3] = {P * (v[0] - 1), P * (v[1] - 1), DIM == 3 ? P * (v[2] - 1) : 0};
+    T *ucl = lds + off_ucl, *r = lds + off_r;
+    const T *__restrict__ u_in = a.u;
+    for (int e = tid; e < Nd; e += NT) {
+      const int i = e % N, j = (e / N) % N, k = DIM == 3 ? e / (N * N) : 0;
+      const int gx = g0[0] + i, gy = g0[1] + j, gz = g0[2] + k;
+      bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
+      if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
+      ucl[e] = bnd ? T(0) : u_in[gx + m * (gy + m * gz)];
+    }
+    for (int e = tid; e < nd; e += NT) {
+      int k[3];
+      decode(e, k);
+      r[e] = a.b[(g0[0] + 1 + k[0]) + m * ((g0[1] + 1 + k[1]) + m * (g0[2] + (DIM == 3 ? 1 : 0) + k[2]))];
+    }
+    PMG_SYNC();
+    // r = b - c (sum_k Kr_k (x) Mr_others) ubar   (closure -> interior)
+    laplace_sf<DIM, PatResidual<P>, NT>(tid, ucl, r, r, a.c, a.tb.Kr, a.tb.Mr, lds + off_abR, ucl);
+    PMG_SYNC();
+    local_solve(tid, lds, a);
+    const T *d = lds + off_d;
+    for (int e = tid; e < nd; e += NT) {
+      int k[3];
+      decode(e, k);
+      const int gi = (g0[0] + 1 + k[0]) + m * ((g0[1] + 1 + k[1]) + m * (g0[2] + (DIM == 3 ? 1 : 0) + k[2]));
+      a.u[gi] += d[e];
+    }
+  }
+
+  // LocalSolve alone on block blk of r_blocks -> d_blocks
+  PMG_INLINE static void local_only(int tid, int blk, T *lds, const SmoothArgs<T> &a) {
+    T *r = lds + off_r;
+    const size_t base = (size_t)blk * nd;
+    for (int e = tid; e < nd; e += NT) r[e] = a.r_blocks[base + e];
+    PMG_SYNC();
+    local_solve(tid, lds, a);
+    const T *d = lds + off_d;
+    for (int e = tid; e < nd; e += NT) a.d_blocks[base + e] = d[e];
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// Operator apply v = A u (or residual r = b - A u) on a Cartesian h-level.  A tile of TC^d
+// cells owns the nodes P*c0 .. P*(c0+TC)-1 per direction (plus the last node of the mesh
+// for tiles at the upper end); it reads the nodes of its cells and of one extra cell below,
+// so every owned node sees all of its cells and each output is written by one workgroup.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct ApplyArgs {
+  const T *Kt, *Mt;
+  T c;
+  int n;       // cells per direction
+  int ntile;   // tiles per direction
+  int n_tiles; // total tiles
+  const T *u;
+  const T *b;  // residual mode
+  T *out;
+};
+
+template <int DIM, typename T, int NT, int P, int TC, bool RESID>
+struct ApplyBody {
+  static constexpr int NI = P * (TC + 1) + 1, NO = P * TC;
+  static constexpr int NId = ipow(NI, DIM), NOd = ipow(NO, DIM);
+  using RS = LapScratch<DIM, NI, NO>;
+  static constexpr int R0 = cmax(NId, RS::cg);
+  static constexpr int R1 = RS::ab;
+  static_assert(DIM == 2 ? NOd <= R0 : NOd <= R1, "output tile must fit its overlay");
+  static constexpr int size = R0 + R1;
+
+  PMG_INLINE static void run(int tid, int blk, T *lds, const ApplyArgs<T> &a) {
+    const int t = xcd_remap(blk, a.n_tiles);
+    const int tt[3] = {t % a.ntile, (t / a.ntile) % a.ntile, DIM == 3 ? t / (a.ntile * a.ntile) : 0};
+    const int m = P * a.n + 1;
+    int c0[3], lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      c0[d] = TC * tt[d];
+      lo[d] = P * (c0[d] - 1);                       // first input node
+      hi[d] = (c0[d] + TC >= a.n) ? m : P * (c0[d] + TC);  // one past the last owned node
+    }
+    // the output tile overlays whatever is dead when the last stage writes it: ab in 3D
+    // (read by stage 2 only), the input tile in 2D (read by stage 1 only)
+    T *in = lds, *ab = lds + R0, *outl = DIM == 3 ? lds + R0 : lds;
+    const T *__restrict__ u = a.u;
+    for (int e = tid; e < NId; e += NT) {
+      const int i = e % NI, j = (e / NI) % NI, k = DIM == 3 ? e / (NI * NI) : 0;
+      const int gx = lo[0] + i, gy = lo[1] + j, gz = DIM == 3 ? lo[2] + k : 0;
+      bool ok = gx > 0 && gx < m - 1 && gy > 0 && gy < m - 1;
+      if (DIM == 3) ok = ok && gz > 0 && gz < m - 1;
+      in[e] = ok ? u[gx + m * (gy + m * gz)] : T(0);
+    }
+    PMG_SYNC();
+    laplace_sf<DIM, PatTile<P, TC>, NT>(tid, in, outl, (const T *)nullptr, a.c, a.Kt, a.Mt, ab, in);
+    PMG_SYNC();
+    const int bx = hi[0] - P * c0[0], by = hi[1] - P * c0[1], bz = DIM == 3 ? hi[2] - P * c0[2] : 1;
+    const int tot = bx * by * bz;
+    for (int e = tid; e < tot; e += NT) {
+      const int ox = e % bx, oy = (e / bx) % by, oz = DIM == 3 ? e / (bx * by) : 0;
+      const int gx = P * c0[0] + ox, gy = P * c0[1] + oy, gz = DIM == 3 ? P * c0[2] + oz : 0;
+      bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
+      if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
+      const int gi = gx + m * (gy + m * gz);
+      T val = bnd ? u[gi] : outl[ox + NO * (oy + NO * oz)];
+      if (RESID) val = a.b[gi] - val;
+      a.out[gi] = val;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// h-transfers between mesh levels (Sec. 2): prolongation = embedding, restriction = its
+// transpose.  1D weights: W1[alpha][a] = coarse cell basis a at the fine node alpha of the
+// two fine cells inside it; Wr[class][t] = restriction weights of a coarse node of class
+// a = K mod P over its fine support (2P-1 nodes, or 4P-1 for a vertex).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct TransferArgs {
+  const T *W1, *Wr;
+  int nc;  // coarse cells per direction
+  const T *in;
+  T *out;
+};
+
+template <int DIM, typename T, int P>
+struct TransferBody {
+  // coarse node index gc -> output (thread per coarse node)
+  PMG_INLINE static void restrict_node(long gc, const TransferArgs<T> &a) {
+    const int mc = P * a.nc + 1, mf = 2 * P * a.nc + 1;
+    int K[3] = {(int)(gc % mc), (int)((gc / mc) % mc), DIM == 3 ? (int)(gc / ((long)mc * mc)) : 1};
+    bool bnd = false;
+    for (int d = 0; d < DIM; ++d) bnd = bnd || K[d] == 0 || K[d] == mc - 1;
+    if (bnd) {
+      a.out[gc] = T(0);
+      return;
+    }
+    int st[3] = {0, 0, 0}, cn[3] = {1, 1, 1}, cl[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+      const int cc = K[d] / P, al = K[d] % P;
+      cl[d] = al;
+      if (al != 0) {
+        st[d] = 2 * P * cc + 1;
+        cn[d] = 2 * P - 1;
+      } else {
+        st[d] = 2 * P * (cc - 1) + 1;
+        cn[d] = 4 * P - 1;
+      }
+    }
+    constexpr int nw = 4 * P - 1;
+    const T *wx = a.Wr + cl[0] * nw, *wy = a.Wr + cl[1] * nw, *wz = a.Wr + cl[2] * nw;
+    T acc = 0;
+    for (int tz = 0; tz < cn[2]; ++tz) {
+      const T fz = DIM == 3 ? wz[tz] : T(1);
+      const long bz = DIM == 3 ? (long)(st[2] + tz) * mf * mf : 0;
+      for (int ty = 0; ty < cn[1]; ++ty) {
+        const T fy = fz * wy[ty];
+        const long by = bz + (long)(st[1] + ty) * mf;
+        T s = 0;
+        for (int tx = 0; tx < cn[0]; ++tx) s += wx[tx] * a.in[by + st[0] + tx];
+        acc += fy * s;
+      }
+    }
+    a.out[gc] = acc;
+  }
+
+  // fine node index gf: out[gf] += sum_coarse W1 in[coarse]  (fine boundary untouched)
+  PMG_INLINE static void prolong_node(long gf, const TransferArgs<T> &a) {
+    const int mc = P * a.nc + 1, mf = 2 * P * a.nc + 1;
+    int F[3] = {(int)(gf % mf), (int)((gf / mf) % mf), DIM == 3 ? (int)(gf / ((long)mf * mf)) : 0};
+    for (int d = 0; d < DIM; ++d)
+      if (F[d] == 0 || F[d] == mf - 1) return;
+    int cb[3] = {0, 0, 0}, al[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+      int cc = F[d] / (2 * P);
+      if (cc > a.nc - 1) cc = a.nc - 1;
+      cb[d] = P * cc;
+      al[d] = F[d] - 2 * P * cc;
+    }
+    const T *wx = a.W1 + al[0] * (P + 1), *wy = a.W1 + al[1] * (P + 1), *wz = a.W1 + al[2] * (P + 1);
+    T acc = 0;
+    const int nz = DIM == 3 ? P + 1 : 1;
+    for (int cz = 0; cz < nz; ++cz) {
+      const int Kz = cb[2] + cz;
+      if (DIM == 3 && (Kz == 0 || Kz == mc - 1)) continue;
+      const T fz = DIM == 3 ? wz[cz] : T(1);
+      for (int cy = 0; cy <= P; ++cy) {
+        const int Ky = cb[1] + cy;
+        if (Ky == 0 || Ky == mc - 1) continue;
+        const T fy = fz * wy[cy];
+        const long base = (long)Ky * mc + (DIM == 3 ? (long)Kz * mc * mc : 0);
+        T s = 0;
+        for (int cx = 0; cx <= P; ++cx) {
+          const int Kx = cb[0] + cx;
+          if (Kx == 0 || Kx == mc - 1) continue;
+          s += wx[cx] * a.in[base + Kx];
+        }
+        acc += fy * s;
+      }
+    }
+    a.out[gf] += acc;
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// Coarsest mesh: z = A_0^{-1} r by fast diagonalization of the Cartesian interior operator,
+// A_0 = c0 sum_k K (x) M (x) M with K S = M S diag(lam), S^T M S = I, so
+// A_0^{-1} = (1/c0) (S (x) S (x) S) diag(1 / (lam_i + lam_j + lam_k)) (S (x) S (x) S)^T.
+// One workgroup; w1/w2 are float64 work arrays of m^d entries.  Boundary: z = r.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct CoarseArgs {
+  const double *S, *lam;
+  double c0inv;
+  int m;   // interior nodes per direction
+  int mt;  // total nodes per direction (m + 2)
+  const T *r;
+  T *z;
+  double *w1, *w2;
+};
+
+template <int DIM, typename T, int NT>
+struct CoarseBody {
+  // w_out(.., a, ..) = sum_i S[i][a] w_in(.., i, ..) (transpose) or sum_a S[i][a] w_in(..a..)
+  PMG_INLINE static void axis(int tid, const CoarseArgs<T> &a, const double *in, double *out, int ax, bool tr) {
+    const int m = a.m, tot = DIM == 3 ? m * m * m : m * m;
+    const int st = ax == 0 ? 1 : (ax == 1 ? m : m * m);
+    for (int e = tid; e < tot; e += NT) {
+      const int o = (e / st) % m, base = e - o * st;
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += (tr ? a.S[i * m + o] : a.S[o * m + i]) * in[base + i * st];
+      out[e] = s;
+    }
+  }
+  PMG_INLINE static void run(int tid, const CoarseArgs<T> &a) {
+    const int m = a.m, mt = a.mt, tot = DIM == 3 ? m * m * m : m * m;
+    const int totall = DIM == 3 ? mt * mt * mt : mt * mt;
+    for (int e = tid; e < totall; e += NT) {  // boundary rows are identity rows
+      const int i = e % mt, j = (e / mt) % mt, k = DIM == 3 ? e / (mt * mt) : 1;
+      bool bnd = i == 0 || i == mt - 1 || j == 0 || j == mt - 1;
+      if (DIM == 3) bnd = bnd || k == 0 || k == mt - 1;
+      if (bnd) a.z[e] = a.r[e];
+    }
+    for (int e = tid; e < tot; e += NT) {
+      const int i = e % m, j = (e / m) % m, k = DIM == 3 ? e / (m * m) : 0;
+      a.w1[e] = (double)a.r[(i + 1) + mt * ((j + 1) + mt * (k + (DIM == 3 ? 1 : 0)))];
+    }
+    PMG_SYNC();
+    double *x = a.w1, *y = a.w2;
+    for (int ax = 0; ax < DIM; ++ax) {
+      axis(tid, a, x, y, ax, true);
+      PMG_SYNC();
+      double *t = x; x = y; y = t;
+    }
+    for (int e = tid; e < tot; e += NT) {
+      const int i = e % m, j = (e / m) % m, k = DIM == 3 ? e / (m * m) : 0;
+      double lsum = a.lam[i] + a.lam[j] + (DIM == 3 ? a.lam[k] : 0.0);
+      x[e] *= a.c0inv / lsum;
+    }
+    PMG_SYNC();
+    for (int ax = 0; ax < DIM; ++ax) {
+      axis(tid, a, x, y, ax, false);
+      PMG_SYNC();
+      double *t = x; x = y; y = t;
+    }
+    for (int e = tid; e < tot; e += NT) {
+      const int i = e % m, j = (e / m) % m, k = DIM == 3 ? e / (m * m) : 0;
+      a.z[(i + 1) + mt * ((j + 1) + mt * (k + (DIM == 3 ? 1 : 0)))] = (T)x[e];
+    }
+  }
+};
+
+}  // namespace pmg

@@ -1,0 +1,76 @@
+// Compile-time dispatch over the supported degrees and p-hierarchies.
+//
+// Hierarchy code 0 is the paper's rule (Sec. 2.2: 1, 3, 7, ... below p, then p); code 1
+// is the one-step hierarchy 1, 2, ..., p (offered for p <= 4).
+#pragma once
+
+#include "bodies.h"
+#include "constants.h"
+
+namespace pmg {
+
+constexpr int kMaxDegree = 8;
+
+// Calls F<P, Degrees<...>>::run(args...) for the runtime (p, code); returns -2 when the
+// combination is not compiled in.
+template <template <int, class> class F, typename... Args>
+int dispatch_hierarchy(int p, int code, Args &&...args) {
+  switch (code * 16 + p) {
+    case 1: return F<1, Degrees<1>>::run(args...);
+    case 2: return F<2, Degrees<1, 2>>::run(args...);
+    case 3: return F<3, Degrees<1, 3>>::run(args...);
+    case 4: return F<4, Degrees<1, 3, 4>>::run(args...);
+    case 5: return F<5, Degrees<1, 3, 5>>::run(args...);
+    case 6: return F<6, Degrees<1, 3, 6>>::run(args...);
+    case 7: return F<7, Degrees<1, 3, 7>>::run(args...);
+    case 8: return F<8, Degrees<1, 3, 7, 8>>::run(args...);
+    case 16 + 1: return F<1, Degrees<1>>::run(args...);
+    case 16 + 2: return F<2, Degrees<1, 2>>::run(args...);
+    case 16 + 3: return F<3, Degrees<1, 2, 3>>::run(args...);
+    case 16 + 4: return F<4, Degrees<1, 2, 3, 4>>::run(args...);
+    default: return -2;
+  }
+}
+
+// Calls F<P>::run(args...) for p = 1..8.
+template <template <int> class F, typename... Args>
+int dispatch_degree(int p, Args &&...args) {
+  switch (p) {
+    case 1: return F<1>::run(args...);
+    case 2: return F<2>::run(args...);
+    case 3: return F<3>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 5: return F<5>::run(args...);
+    case 6: return F<6>::run(args...);
+    case 7: return F<7>::run(args...);
+    case 8: return F<8>::run(args...);
+    default: return -2;
+  }
+}
+
+// Hierarchy code of a degree list (ascending), or -1 if not supported.
+inline int hierarchy_code(int p, const int *deg, int L) {
+  // paper rule
+  {
+    int q[8], k = 0, x = 1;
+    while (x < p) { q[k++] = x; x = 2 * x + 1; }
+    q[k++] = p;
+    if (k == L) {
+      bool same = true;
+      for (int i = 0; i < L; ++i) same = same && q[i] == deg[i];
+      if (same) return 0;
+    }
+  }
+  if (p <= 4 && L == p) {
+    bool same = true;
+    for (int i = 0; i < L; ++i) same = same && deg[i] == i + 1;
+    if (same) return 1;
+  }
+  return -1;
+}
+
+// Threads per workgroup of the patch kernel and of the apply kernel, by degree.
+constexpr int patch_threads(int p) { return p <= 2 ? 64 : (p <= 4 ? 128 : 256); }
+constexpr int apply_threads(int p) { return p <= 2 ? 128 : 128; }
+
+}  // namespace pmg

@@ -1,0 +1,72 @@
+// Host-side launchers of the HIP kernels (implemented in kernels.hip and blas.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bodies.h"
+
+namespace pmg {
+
+// Workgroup arena of a kernel: in LDS when it fits the device limit, otherwise a slice of
+// a global-memory buffer (then the grid is capped at `slots` workgroups that loop).
+struct Arena {
+  void *global = nullptr;  // device buffer, or nullptr when every kernel fits in LDS
+  int slots = 0;           // workgroups the global buffer has room for
+  size_t lds_max = 0;      // bytes of LDS a workgroup may use on this device
+};
+
+// Kernel launchers of one (dimension, precision); instantiated in kernels_<d>d_<prec>.hip.
+template <int DIM, typename T>
+struct Launchers {
+  static size_t patch_bytes(int p, int hcode);
+  static size_t apply_bytes(int p);
+  static int smooth(int p, int hcode, const SmoothArgs<T> &a, const Arena &ar, hipStream_t s);
+  static int local(int p, int hcode, const SmoothArgs<T> &a, int nb, const Arena &ar, hipStream_t s);
+  static int apply(int p, bool resid, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s);
+  static int restrict_(int p, const TransferArgs<T> &a, hipStream_t s);
+  static int prolong(int p, const TransferArgs<T> &a, hipStream_t s);
+  static int coarse(const CoarseArgs<T> &a, hipStream_t s);
+};
+
+// Bytes of the per-workgroup arena of each kernel family (0 if not compiled in).
+size_t patch_arena_bytes(int dim, int prec, int p, int hcode);
+size_t apply_arena_bytes(int dim, int prec, int p);
+
+template <typename T>
+int launch_smooth_color(int dim, int p, int hcode, const SmoothArgs<T> &a, const Arena &ar, hipStream_t s);
+template <typename T>
+int launch_local_only(int dim, int p, int hcode, const SmoothArgs<T> &a, int n_blocks, const Arena &ar,
+                      hipStream_t s);
+template <typename T>
+int launch_apply(int dim, int p, bool resid, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s);
+template <typename T>
+int launch_restrict(int dim, int p, const TransferArgs<T> &a, hipStream_t s);
+template <typename T>
+int launch_prolong_add(int dim, int p, const TransferArgs<T> &a, hipStream_t s);
+template <typename T>
+int launch_coarse(int dim, const CoarseArgs<T> &a, hipStream_t s);
+
+// ---- vector kernels (blas.hip) ----
+constexpr int kRedBlocks = 512;  // fixed grid of the deterministic reductions
+enum Scal { S_RZ = 0, S_PQ, S_ALPHA, S_RR, S_ZRN, S_ZRO, S_BETA, S_BB, S_COUNT };
+
+// partial[k*kRedBlocks + b] = block b's share of (x, y_k), k < ny (1 or 2)
+int launch_dot_partial(const double *x, const double *y0, const double *y1, long n, double *partial,
+                       hipStream_t s);
+// final sums of the partials; mode selects the follow-up scalar update:
+//  0: scal[i0] = (x,y0)                      1: scal[S_PQ] = (p,q), scal[S_ALPHA] = rz/pq
+//  2: scal[S_ZRN], scal[S_ZRO]; beta = (zrn - zro)/rz; rz = zrn
+int launch_dot_final(const double *partial, int ny, int mode, int i0, double *scal, hipStream_t s);
+// x += alpha p; rn = ro - alpha q; partial (rn, rn)
+int launch_fcg_xr(double *x, const double *ro, double *rn, const double *p, const double *q, const double *scal,
+                  long n, double *partial, hipStream_t s);
+// p = z + beta p
+int launch_fcg_p(double *p, const double *z, const double *scal, long n, hipStream_t s);
+int launch_copy(double *dst, const double *src, long n, hipStream_t s);
+int launch_cast_d2f(const double *in, float *out, long n, hipStream_t s);
+int launch_cast_f2d(const float *in, double *out, long n, hipStream_t s);
+// z = 0 on interior nodes, z = r on boundary nodes of an m^dim node grid
+template <typename T>
+int launch_init_z(int dim, int m, T *z, const T *r, hipStream_t s);
+
+}  // namespace pmg

@@ -1,0 +1,258 @@
+// Sum-factorized 1D contractions on small tensors held in LDS.
+//
+// A tensor of extents (E0, E1, E2) is stored x fastest.  A contraction along axis AX
+// replaces extent E_AX = NIN by NOUT: out(.., o, ..) = sum_i Mat[o][i] in(.., i, ..).
+// Each thread owns whole pencils (all NIN inputs of one line), loads them into
+// registers once and produces every output of the line, so one LDS read feeds up to
+// 2*NOUT fused multiply-adds.  Matrices are row-major NOUT x NIN tables in global memory
+// with wave-uniform addresses (read through the scalar cache) and a compile-time
+// sparsity pattern: row o touches columns [Pat::lo(o), Pat::hi(o)) only.
+//
+// The bodies are __host__ __device__: on the device tid/NT are the workgroup's threads,
+// on the host (NT = 1) the same code runs sequentially for index and bounds checks.
+#pragma once
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define PMG_HD __host__ __device__
+#define PMG_INLINE __host__ __device__ inline __attribute__((always_inline))
+#else
+#define PMG_HD
+#define PMG_INLINE inline
+#endif
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PMG_SYNC() __syncthreads()
+#else
+#define PMG_SYNC() ((void)0)
+#endif
+
+namespace pmg {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// ---- sparsity patterns of the 1D matrices ---------------------------------------------
+// Patch interior matrix of degree Q: rows/cols are the 2Q-1 interior nodes of two cells.
+template <int Q>
+struct PatInterior {
+  static constexpr int nout = 2 * Q - 1, nin = 2 * Q - 1;
+  PMG_HD static constexpr int lo(int o) { return (o + 1 > Q) ? Q - 1 : 0; }
+  PMG_HD static constexpr int hi(int o) { return (o + 1 < Q) ? Q : 2 * Q - 1; }
+};
+// Patch residual of degree P: interior rows (2P-1), closure columns (2P+1).
+template <int P>
+struct PatResidual {
+  static constexpr int nout = 2 * P - 1, nin = 2 * P + 1;
+  PMG_HD static constexpr int lo(int o) { return (o + 1 > P) ? P : 0; }
+  PMG_HD static constexpr int hi(int o) { return (o + 1 < P) ? P + 1 : 2 * P + 1; }
+};
+// Embedding of degree QC into degree QF on a patch: fine interior rows, coarse interior cols.
+template <int QF, int QC>
+struct PatProlong {
+  static constexpr int nout = 2 * QF - 1, nin = 2 * QC - 1;
+  PMG_HD static constexpr int lo(int o) { return (o + 1 >= QF) ? QC - 1 : 0; }
+  PMG_HD static constexpr int hi(int o) { return (o + 1 <= QF) ? QC : 2 * QC - 1; }
+};
+// Its transpose: coarse interior rows, fine interior cols.
+template <int QF, int QC>
+struct PatRestrict {
+  static constexpr int nout = 2 * QC - 1, nin = 2 * QF - 1;
+  PMG_HD static constexpr int lo(int o) { return (o + 1 > QC) ? QF - 1 : 0; }
+  PMG_HD static constexpr int hi(int o) { return (o + 1 < QC) ? QF : 2 * QF - 1; }
+};
+// Apply tile of TC cells of degree P: output nodes P*c0 + o (o < P*TC), input nodes
+// P*(c0-1) + i (i <= P*(TC+1)); row o touches the cells containing its node.
+template <int P, int TC>
+struct PatTile {
+  static constexpr int nout = P * TC, nin = P * (TC + 1) + 1;
+  PMG_HD static constexpr int lo(int o) { return (o % P == 0) ? P * (o / P) : P * (o / P + 1); }
+  PMG_HD static constexpr int hi(int o) { return P * (o / P + 1) + P + 1; }
+};
+
+// ---- axis bookkeeping -----------------------------------------------------------------
+template <int AX, int E0, int E1, int E2, int NOUT>
+struct Axis {
+  static constexpr int NIN = AX == 0 ? E0 : (AX == 1 ? E1 : E2);
+  static constexpr int NPEN = E0 * E1 * E2 / NIN;
+  static constexpr int IS = AX == 0 ? 1 : (AX == 1 ? E0 : E0 * E1);  // input stride on AX
+  static constexpr int OS = AX == 0 ? 1 : (AX == 1 ? E0 : E0 * E1);  // output stride on AX
+  PMG_INLINE static void base(int pen, int &ib, int &ob) {
+    if (AX == 0) {
+      ib = pen * E0;
+      ob = pen * NOUT;
+    } else if (AX == 1) {
+      int i = pen % E0, k = pen / E0;
+      ib = i + E0 * E1 * k;
+      ob = i + E0 * NOUT * k;
+    } else {
+      ib = pen;
+      ob = pen;
+    }
+  }
+};
+
+// oa = A in, ob = B in  (same pattern)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
+PMG_INLINE void contract2(int tid, const T *in, T *oa, const T *__restrict__ A, T *ob,
+                          const T *__restrict__ B) {
+  using X = Axis<AX, E0, E1, E2, Pat::nout>;
+  static_assert(X::NIN == Pat::nin, "extent mismatch");
+  for (int pen = tid; pen < X::NPEN; pen += NT) {
+    int ib, obs;
+    X::base(pen, ib, obs);
+    T v[Pat::nin];
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::IS];
+#pragma unroll
+    for (int o = 0; o < Pat::nout; ++o) {
+      T sa = 0, sb = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) {
+          sa += A[o * Pat::nin + i] * v[i];
+          sb += B[o * Pat::nin + i] * v[i];
+        }
+      oa[obs + o * X::OS] = sa;
+      ob[obs + o * X::OS] = sb;
+    }
+  }
+}
+
+// oc = M ia, og = K ia + M ib
+template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
+PMG_INLINE void contract_pair(int tid, const T *ia, const T *ib_, T *oc, T *og,
+                              const T *__restrict__ M, const T *__restrict__ K) {
+  using X = Axis<AX, E0, E1, E2, Pat::nout>;
+  static_assert(X::NIN == Pat::nin, "extent mismatch");
+  for (int pen = tid; pen < X::NPEN; pen += NT) {
+    int ib, obs;
+    X::base(pen, ib, obs);
+    T va[Pat::nin], vb[Pat::nin];
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) {
+      va[i] = ia[ib + i * X::IS];
+      vb[i] = ib_[ib + i * X::IS];
+    }
+#pragma unroll
+    for (int o = 0; o < Pat::nout; ++o) {
+      T sc = 0, sg = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) {
+          T m = M[o * Pat::nin + i];
+          sc += m * va[i];
+          sg += K[o * Pat::nin + i] * va[i] + m * vb[i];
+        }
+      oc[obs + o * X::OS] = sc;
+      og[obs + o * X::OS] = sg;
+    }
+  }
+}
+
+// out = base - s (K ia + M ib)   (base != nullptr), or out = s (K ia + M ib)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
+PMG_INLINE void contract_final(int tid, const T *ia, const T *ib_, T *out, const T *base, T s,
+                               const T *__restrict__ K, const T *__restrict__ M) {
+  using X = Axis<AX, E0, E1, E2, Pat::nout>;
+  static_assert(X::NIN == Pat::nin, "extent mismatch");
+  for (int pen = tid; pen < X::NPEN; pen += NT) {
+    int ib, obs;
+    X::base(pen, ib, obs);
+    T va[Pat::nin], vb[Pat::nin];
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) {
+      va[i] = ia[ib + i * X::IS];
+      vb[i] = ib_[ib + i * X::IS];
+    }
+#pragma unroll
+    for (int o = 0; o < Pat::nout; ++o) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += K[o * Pat::nin + i] * va[i] + M[o * Pat::nin + i] * vb[i];
+      const int oi = obs + o * X::OS;
+      out[oi] = base ? base[oi] - s * acc : s * acc;
+    }
+  }
+}
+
+// out = Mat in  (ADD: out += Mat in)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, bool ADD, typename T>
+PMG_INLINE void contract1(int tid, const T *in, T *out, const T *__restrict__ Mat) {
+  using X = Axis<AX, E0, E1, E2, Pat::nout>;
+  static_assert(X::NIN == Pat::nin, "extent mismatch");
+  for (int pen = tid; pen < X::NPEN; pen += NT) {
+    int ib, obs;
+    X::base(pen, ib, obs);
+    T v[Pat::nin];
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::IS];
+#pragma unroll
+    for (int o = 0; o < Pat::nout; ++o) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * v[i];
+      const int oi = obs + o * X::OS;
+      if (ADD)
+        out[oi] += acc;
+      else
+        out[oi] = acc;
+    }
+  }
+}
+
+// ---- whole-tensor Laplacian pieces ----------------------------------------------------
+// out = base - s * (sum_k K_k (x) M_others) in,  in: (N,N,N) or (N,N) through a pattern
+// Pat (N = Pat::nin -> n = Pat::nout per axis).  Scratch: ab (2 n N^(d-1)), cg (2 n^2 N).
+// in and cg may alias (in is dead after the first stage).
+template <int DIM, class Pat, int NT, typename T>
+PMG_INLINE void laplace_sf(int tid, const T *in, T *out, const T *base, T s, const T *K, const T *M,
+                           T *ab, T *cg) {
+  constexpr int N = Pat::nin, n = Pat::nout;
+  if constexpr (DIM == 3) {
+    constexpr int SA = n * N * N, SC = n * n * N;
+    contract2<0, N, N, N, Pat, NT>(tid, in, ab, M, ab + SA, K);  // A = Mx u, B = Kx u
+    PMG_SYNC();
+    contract_pair<1, n, N, N, Pat, NT>(tid, ab, ab + SA, cg, cg + SC, M, K);  // C = My A, G = Ky A + My B
+    PMG_SYNC();
+    contract_final<2, n, n, N, Pat, NT>(tid, cg, cg + SC, out, base, s, K, M);  // Kz C + Mz G
+  } else {
+    constexpr int SA = n * N;
+    contract2<0, N, N, 1, Pat, NT>(tid, in, ab, M, ab + SA, K);
+    PMG_SYNC();
+    contract_final<1, n, N, 1, Pat, NT>(tid, ab, ab + SA, out, base, s, K, M);  // Ky A + My B
+  }
+}
+
+constexpr int lap_ab(int dim, int N, int n) { return dim == 3 ? 2 * n * N * N : 2 * n * N; }
+constexpr int lap_cg(int dim, int N, int n) { return dim == 3 ? 2 * n * n * N : 0; }
+template <int DIM, int N, int n>
+struct LapScratch {
+  static constexpr int ab = lap_ab(DIM, N, n);
+  static constexpr int cg = lap_cg(DIM, N, n);
+};
+
+// out (= or +=) Kronecker product of the 1D matrix Mat (pattern Pat) in every direction.
+// Scratch t1 (NOUT NIN^(d-1)), t2 (NOUT^2 NIN) for 3D.
+template <int DIM, class Pat, int NT, bool ADD, typename T>
+PMG_INLINE void kron_all(int tid, const T *in, T *out, const T *Mat, T *t1, T *t2) {
+  constexpr int I = Pat::nin, O = Pat::nout;
+  if constexpr (DIM == 3) {
+    contract1<0, I, I, I, Pat, NT, false>(tid, in, t1, Mat);
+    PMG_SYNC();
+    contract1<1, O, I, I, Pat, NT, false>(tid, t1, t2, Mat);
+    PMG_SYNC();
+    contract1<2, O, O, I, Pat, NT, ADD>(tid, t2, out, Mat);
+  } else {
+    contract1<0, I, I, 1, Pat, NT, false>(tid, in, t1, Mat);
+    PMG_SYNC();
+    contract1<1, O, I, 1, Pat, NT, ADD>(tid, t1, out, Mat);
+  }
+}
+
+constexpr int kron_t1(int dim, int I, int O) { return dim == 3 ? O * I * I : O * I; }
+constexpr int kron_t2(int dim, int I, int O) { return dim == 3 ? O * O * I : 0; }
+
+}  // namespace pmg

@@ -1,0 +1,287 @@
+"""Python binding of libpmg.so: argument marshalling only.
+
+Every function has the name of the C entry point it wraps (without the pmg_ prefix) and
+calls it once; all work runs in the library's HIP kernels.  Device vectors are
+contiguous torch tensors on the current HIP device (float64 for PMG_FP64 calls,
+float32 for PMG_FP32), passed by pointer together with torch's current stream.  The
+library must have been built (python -m paper_2512_02577_amd.build); there is no
+fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmg.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_STATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+FP64, FP32 = 0, 1
+LOCAL_HALF_V, LOCAL_FULL_V = 0, 1
+
+
+class PmgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"pmg status {status}: {message}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("local_solver", ctypes.c_int), ("n_local_iter", ctypes.c_int), ("n_pre", ctypes.c_int),
+                ("n_post", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("n_omega", ctypes.c_int), ("omega", ctypes.c_double * 8)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("status", ctypes.c_int)]
+
+
+_lib = None
+_vp, _ip, _dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libpmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2512_02577_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        sig = {
+            "pmg_last_error": (ctypes.c_char_p, []),
+            "pmg_default_config": (None, [P(Config)]),
+            "pmg_setup_mesh": (_ip, [_ip, _ip, _ip, P(_dp), P(_vp)]),
+            "pmg_mesh_levels": (_ip, [_vp, P(_ip), P(_ip), P(ctypes.c_int32)]),
+            "pmg_destroy_mesh": (None, [_vp]),
+            "pmg_setup_dofmap": (_ip, [_vp, _ip, P(ctypes.c_int32), _ip, P(Config), P(_vp)]),
+            "pmg_problem_sizes": (_ip, [_vp, P(_ip), P(_ip), P(_ip), P(ctypes.c_int32), P(ctypes.c_int64),
+                                        P(ctypes.c_int64), P(ctypes.c_int32), P(_dp)]),
+            "pmg_export_maps": (_ip, [_vp, _ip, _ip, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32),
+                                      P(ctypes.c_uint8)]),
+            "pmg_device_init": (_ip, [_vp]),
+            "pmg_apply_operator": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp]),
+            "pmg_residual": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp, _vp]),
+            "pmg_smooth": (_ip, [_vp, _ip, _ip, _ip, _vp, _vp, _vp]),
+            "pmg_local_solve": (_ip, [_vp, _ip, _ip, _ip, _ip, _vp, _vp, _vp]),
+            "pmg_restrict": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp]),
+            "pmg_prolongate_add": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp]),
+            "pmg_coarse_solve": (_ip, [_vp, _ip, _vp, _vp, _vp]),
+            "pmg_vcycle": (_ip, [_vp, _ip, _vp, _vp, _vp]),
+            "pmg_solve": (_ip, [_vp, _ip, _vp, _vp, _ip, P(SolveInfo), _vp]),
+            "pmg_destroy_problem": (None, [_vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().pmg_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc != OK:
+        raise PmgError(rc, last_error())
+    return rc
+
+
+def default_config() -> Config:
+    c = Config()
+    lib().pmg_default_config(ctypes.byref(c))
+    return c
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _prec_of(t) -> int:
+    import torch
+
+    if t.dtype == torch.float64:
+        return FP64
+    if t.dtype == torch.float32:
+        return FP32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _nodes(pr: "Problem", hlevel: int):
+    """Expected vector length on an h-level, or None when the level is out of range
+    (the library then rejects the call with its own error)."""
+    return pr.n_nodes[hlevel] if 0 <= hlevel < len(pr.n_nodes) else None
+
+
+def _ptr(t, n: int | None = None, dtype=None):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("vectors must be contiguous device tensors")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} entries, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """Handle of a pmg_mesh (setup_mesh)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self.handle = handle
+
+    def levels(self) -> list[int]:
+        nh = ctypes.c_int()
+        _check(lib().pmg_mesh_levels(self.handle, None, ctypes.byref(nh), None))
+        out = (ctypes.c_int32 * nh.value)()
+        _check(lib().pmg_mesh_levels(self.handle, None, None, out))
+        return list(out)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.pmg_destroy_mesh(self.handle)
+            self.handle = None
+
+
+class Problem:
+    """Handle of a pmg_problem (setup_dofmap) with its sizes."""
+
+    def __init__(self, handle: ctypes.c_void_p, degree: int):
+        self.handle = handle
+        self.p = degree
+        dim, nh, npl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().pmg_problem_sizes(handle, ctypes.byref(dim), ctypes.byref(nh), ctypes.byref(npl), None, None,
+                                       None, None, None))
+        self.dim, self.n_hlevels, self.n_plevels = dim.value, nh.value, npl.value
+        cells = (ctypes.c_int32 * nh.value)()
+        nodes = (ctypes.c_int64 * nh.value)()
+        patches = (ctypes.c_int64 * nh.value)()
+        deg = (ctypes.c_int32 * npl.value)()
+        om = (ctypes.c_double * npl.value)()
+        _check(lib().pmg_problem_sizes(handle, None, None, None, cells, nodes, patches, deg, om))
+        self.cells, self.n_nodes, self.n_patches = list(cells), list(nodes), list(patches)
+        self.degrees, self.omega = list(deg), list(om)
+        self.finest = nh.value - 1
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.pmg_destroy_problem(self.handle)
+            self.handle = None
+
+
+def setup_mesh(dim: int, n: int, n_hlevels: int = 0, vertices: np.ndarray | None = None) -> Mesh:
+    h = ctypes.c_void_p()
+    vp = None
+    if vertices is not None:
+        vertices = np.ascontiguousarray(vertices, dtype=np.float64)
+        vp = vertices.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().pmg_setup_mesh(dim, n, n_hlevels, vp, ctypes.byref(h)))
+    return Mesh(h)
+
+
+def setup_dofmap(mesh: Mesh, degree: int, p_levels=None, config: Config | None = None) -> Problem:
+    h = ctypes.c_void_p()
+    lv, nl = None, 0
+    if p_levels is not None:
+        nl = len(p_levels)
+        lv = (ctypes.c_int32 * nl)(*p_levels)
+    cfg = ctypes.byref(config) if config is not None else None
+    _check(lib().pmg_setup_dofmap(mesh.handle, degree, lv, nl, cfg, ctypes.byref(h)))
+    return Problem(h, degree)
+
+
+def export_maps(pr: Problem, hlevel: int, plevel: int) -> dict[str, np.ndarray]:
+    n = pr.cells[hlevel]
+    q = pr.degrees[plevel]
+    d = pr.dim
+    cd = np.empty((n ** d, (q + 1) ** d), dtype=np.int32)
+    npch = (n - 1) ** d
+    pi = np.empty((npch, (2 * q - 1) ** d), dtype=np.int32)
+    pc = np.empty((npch, (2 * q + 1) ** d), dtype=np.int32)
+    col = np.empty(npch, dtype=np.uint8)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    _check(lib().pmg_export_maps(pr.handle, hlevel, plevel, cd.ctypes.data_as(P32), pi.ctypes.data_as(P32),
+                                 pc.ctypes.data_as(P32), col.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return {"cell_dofs": cd, "patch_interior": pi, "patch_closure": pc, "patch_color": col}
+
+
+def device_init(pr: Problem) -> None:
+    _check(lib().pmg_device_init(pr.handle))
+
+
+def apply_operator(pr: Problem, hlevel: int, u, v) -> None:
+    n = _nodes(pr, hlevel)
+    _check(lib().pmg_apply_operator(pr.handle, hlevel, _prec_of(u), _ptr(u, n), _ptr(v, n, u.dtype), _stream()))
+
+
+def residual(pr: Problem, hlevel: int, b, u, r) -> None:
+    n = _nodes(pr, hlevel)
+    _check(lib().pmg_residual(pr.handle, hlevel, _prec_of(u), _ptr(b, n, u.dtype), _ptr(u, n), _ptr(r, n, u.dtype),
+                              _stream()))
+
+
+def smooth(pr: Problem, hlevel: int, u, b, color_dir: int = 1) -> None:
+    n = _nodes(pr, hlevel)
+    _check(lib().pmg_smooth(pr.handle, hlevel, _prec_of(u), color_dir, _ptr(u, n), _ptr(b, n, u.dtype), _stream()))
+
+
+def local_solve(pr: Problem, hlevel: int, r, d, first_patch: int = 0) -> None:
+    blk = (2 * pr.p - 1) ** pr.dim
+    if r.numel() % blk or d.numel() != r.numel():
+        raise ValueError("r and d must hold whole patch-interior blocks")
+    _check(lib().pmg_local_solve(pr.handle, hlevel, _prec_of(r), first_patch, r.numel() // blk, _ptr(r),
+                                 _ptr(d, dtype=r.dtype), _stream()))
+
+
+def restrict(pr: Problem, hlevel: int, fine, coarse) -> None:
+    _check(lib().pmg_restrict(pr.handle, hlevel, _prec_of(fine), _ptr(fine, _nodes(pr, hlevel)),
+                              _ptr(coarse, _nodes(pr, hlevel - 1), fine.dtype), _stream()))
+
+
+def prolongate_add(pr: Problem, hlevel: int, coarse, fine) -> None:
+    _check(lib().pmg_prolongate_add(pr.handle, hlevel, _prec_of(fine),
+                                    _ptr(coarse, _nodes(pr, hlevel - 1), fine.dtype),
+                                    _ptr(fine, _nodes(pr, hlevel)), _stream()))
+
+
+def coarse_solve(pr: Problem, r, z) -> None:
+    n = pr.n_nodes[0]
+    _check(lib().pmg_coarse_solve(pr.handle, _prec_of(r), _ptr(r, n), _ptr(z, n, r.dtype), _stream()))
+
+
+def vcycle(pr: Problem, r, z, mg_prec: int = FP64) -> None:
+    import torch
+
+    n = pr.n_nodes[pr.finest]
+    _check(lib().pmg_vcycle(pr.handle, mg_prec, _ptr(r, n, torch.float64), _ptr(z, n, torch.float64), _stream()))
+
+
+def solve(pr: Problem, b, x, mg_prec: int = FP64, x_is_initial_guess: bool = False,
+          raise_on_failure: bool = True) -> SolveInfo:
+    import torch
+
+    n = pr.n_nodes[pr.finest]
+    info = SolveInfo()
+    rc = lib().pmg_solve(pr.handle, mg_prec, _ptr(b, n, torch.float64), _ptr(x, n, torch.float64),
+                         int(x_is_initial_guess), ctypes.byref(info), _stream())
+    if rc != OK and raise_on_failure:
+        raise PmgError(rc, last_error())
+    return info
+
+
+def make_problem(dim: int, n: int, p: int, p_levels=None, n_hlevels: int = 0, config: Config | None = None,
+                 device: bool = True) -> Problem:
+    """setup_mesh + setup_dofmap (+ device_init)."""
+    mesh = setup_mesh(dim, n, n_hlevels)
+    pr = setup_dofmap(mesh, p, p_levels, config)
+    pr._mesh = mesh
+    if device:
+        device_init(pr)
+    return pr

@@ -1,0 +1,116 @@
+"""The HIP kernels' bodies executed on the CPU (one thread per workgroup, exactly sized
+arena) against the oracle.  This pins the index arithmetic, LDS layouts and 1D tables
+of every kernel family before any GPU run; the GPU parity tests then check the same
+bodies on gfx950."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from oracle.assembly import stiffness_matrix
+from oracle.mesh import StructuredMesh, p_hierarchy
+from oracle.smoother import LevelSmoother
+from oracle.solver import MultigridProblem
+from oracle.transfer import h_prolongation
+from paper_2512_02577_amd.inputs import rhs_vector
+
+EMU = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2512_02577_amd",
+                   "libpmg_hostemu.so")
+DP = ctypes.POINTER(ctypes.c_double)
+
+
+@pytest.fixture(scope="module")
+def emu():
+    if not os.path.exists(EMU):
+        pytest.fail("libpmg_hostemu.so is not built (python -m paper_2512_02577_amd.build)")
+    return ctypes.CDLL(EMU)
+
+
+def P(a):
+    return a.ctypes.data_as(DP)
+
+
+def ci(a):
+    return (ctypes.c_int * len(a))(*a)
+
+
+def cd(a):
+    return (ctypes.c_double * len(a))(*a)
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 4, 1), (2, 5, 2), (2, 5, 3), (2, 3, 7), (2, 3, 8), (3, 3, 1), (3, 5, 2),
+                                     (3, 4, 3), (3, 3, 4), (3, 3, 5), (3, 2, 6), (3, 2, 7), (3, 2, 8)])
+def test_apply_and_residual(emu, dim, n, p):
+    A = stiffness_matrix(StructuredMesh(dim, n), p)
+    u = np.random.default_rng(1).uniform(-1, 1, A.shape[0])
+    b = rhs_vector(dim, n, p, 2)
+    v = np.zeros_like(u)
+    r = np.zeros_like(u)
+    assert emu.pmgemu_apply(dim, n, p, 0, P(u), P(b), P(v)) == 0
+    assert emu.pmgemu_apply(dim, n, p, 1, P(u), P(b), P(r)) == 0
+    ref = A @ u
+    s = abs(ref).max()
+    assert abs(v - ref).max() <= 1e-13 * s
+    assert abs(r - (b - ref)).max() <= 1e-13 * s
+
+
+CASES = [(2, 4, 2, None, "half"), (2, 5, 3, [1, 2, 3], "half"), (2, 4, 3, None, "full"), (3, 3, 2, None, "half"),
+         (3, 4, 4, None, "half"), (3, 3, 4, None, "full"), (3, 3, 4, [1, 2, 3, 4], "half"), (2, 4, 7, None, "half"),
+         (2, 3, 8, None, "full"), (3, 2, 1, None, "half"), (3, 2, 5, None, "half")]
+
+
+@pytest.mark.parametrize("dim,n,p,lv,local", CASES)
+def test_smoother(emu, dim, n, p, lv, local):
+    deg = lv or p_hierarchy(p)
+    om = [1.0] + [0.5 + 0.05 * l for l in range(1, len(deg))]
+    ls = LevelSmoother(StructuredMesh(dim, n), deg, omega=om, local=local)
+    b = rhs_vector(dim, n, p, 3)
+    u0 = np.random.default_rng(4).uniform(-1, 1, len(b))
+    for it in (1, 2):
+        ls.n_local_iter = it
+        for direction in (1, -1):
+            ref = ls.smooth(u0, b, descending=direction < 0)
+            u = u0.copy()
+            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), it, direction,
+                                     P(u), P(b)) == 0
+            assert abs(u - ref).max() <= 1e-12 * abs(ref).max()
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (3, 4), (3, 2)])
+def test_local_solve(emu, dim, p):
+    deg = p_hierarchy(p)
+    om = [1.0] + [0.6] * (len(deg) - 1)
+    ls = LevelSmoother(StructuredMesh(dim, 3), deg, omega=om, local="half")
+    nb = ls.interior[-1].shape[0]
+    nd = ls.interior[-1].shape[1]
+    r = np.random.default_rng(0).uniform(-1, 1, nb * nd)
+    d = np.zeros_like(r)
+    assert emu.pmgemu_local_solve(dim, 3, p, ci(deg), len(deg), cd(om), 0, 1, nb, P(r), P(d)) == 0
+    for j in range(nb):
+        ref = ls.local_solve(j, r[j * nd:(j + 1) * nd])
+        assert abs(d[j * nd:(j + 1) * nd] - ref).max() <= 1e-13 * abs(ref).max()
+
+
+@pytest.mark.parametrize("dim,nc,p", [(2, 2, 1), (2, 3, 3), (3, 2, 2), (3, 2, 4), (2, 2, 8), (3, 3, 1), (3, 2, 7)])
+def test_h_transfers(emu, dim, nc, p):
+    Ph = h_prolongation(dim, nc, p)
+    rng = np.random.default_rng(5)
+    fine = rng.uniform(-1, 1, Ph.shape[0])
+    coarse = rng.uniform(-1, 1, Ph.shape[1])
+    outc = np.zeros(Ph.shape[1])
+    assert emu.pmgemu_transfer(dim, nc, p, 1, P(fine), P(outc)) == 0
+    outf = fine.copy()
+    assert emu.pmgemu_transfer(dim, nc, p, 0, P(coarse), P(outf)) == 0
+    assert abs(outc - Ph.T @ fine).max() <= 1e-13 * abs(outc).max()
+    assert abs(outf - (fine + Ph @ coarse)).max() <= 1e-13 * abs(outf).max()
+
+
+@pytest.mark.parametrize("dim,n0,p", [(2, 2, 3), (3, 2, 4), (3, 3, 2), (2, 3, 8), (3, 2, 1)])
+def test_coarse_solve(emu, dim, n0, p):
+    pb = MultigridProblem(dim, n0, p)
+    r = np.random.default_rng(7).uniform(-1, 1, pb.N)
+    z = np.zeros_like(r)
+    assert emu.pmgemu_coarse_solve(dim, n0, p, P(r), P(z)) == 0
+    ref = pb.coarse_solve(r)
+    assert abs(z - ref).max() <= 1e-12 * abs(ref).max()
