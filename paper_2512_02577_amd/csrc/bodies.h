@@ -125,12 +125,12 @@ struct PatchBody {
   PMG_INLINE static void cycle(int tid, T *lds, const DevTabs<T> &tb, T c, T cinv, const T *r, T *d,
                                bool full) {
     if constexpr (l == 0) {
-      if (tid == 0) d[0] = cinv * tb.invD[0][0] * r[0];  // exact 1x1 solve
+      if (tid == 0) d[0] = cinv * as_const(tb.invD[0])[0] * r[0];  // exact 1x1 solve
       PMG_SYNC();
     } else {
       constexpr int q = qd(l), qc = qd(l - 1), ndq = ndl(l);
       constexpr int t1size = DIM == 3 ? cmax(kron_t1(DIM, nl(l), nl(l - 1)), kron_t1(DIM, nl(l - 1), nl(l))) : 0;
-      const T *__restrict__ invD = tb.invD[l];
+      const cptr<T> invD = as_const(tb.invD[l]);
       for (int e = tid; e < ndq; e += NT) d[e] = cinv * invD[e] * r[e];  // pre-smoothing
       PMG_SYNC();
       T *res = lds + off_res;
@@ -291,96 +291,101 @@ struct ApplyBody {
 
 // ---------------------------------------------------------------------------------------
 // h-transfers between mesh levels (Sec. 2): prolongation = embedding, restriction = its
-// transpose.  1D weights: W1[alpha][a] = coarse cell basis a at the fine node alpha of the
-// two fine cells inside it; Wr[class][t] = restriction weights of a coarse node of class
-// a = K mod P over its fine support (2P-1 nodes, or 4P-1 for a vertex).
+// transpose.  With the Dirichlet rows and columns removed both are Kronecker products of
+// one masked 1D matrix per direction, so each is applied as DIM passes of a 1D transfer,
+// one thread per output entry.  1D weights: W1[alpha][a] = coarse cell basis a at the fine
+// node alpha of the two fine cells inside the coarse cell; Wr[class][t] = restriction
+// weights of a coarse node of class a = K mod P over its fine support (2P-1 nodes, 4P-1
+// for a vertex).
 // ---------------------------------------------------------------------------------------
 template <typename T>
 struct TransferArgs {
   const T *W1, *Wr;
-  int nc;  // coarse cells per direction
+  int nc;           // coarse cells per direction
+  const T *in;
+  T *out;
+  T *w1, *w2;       // intermediates: >= mf*mf*mc and >= mf*mc*mc entries
+};
+
+template <typename T>
+struct PassArgs {
+  const T *W1, *Wr;
+  int nc;
+  int ax;           // contracted axis
+  int ie[3], oe[3]; // input and output extents (x, y, z); 1 for unused axes
   const T *in;
   T *out;
 };
 
-template <int DIM, typename T, int P>
-struct TransferBody {
-  // coarse node index gc -> output (thread per coarse node)
-  PMG_INLINE static void restrict_node(long gc, const TransferArgs<T> &a) {
-    const int mc = P * a.nc + 1, mf = 2 * P * a.nc + 1;
-    int K[3] = {(int)(gc % mc), (int)((gc / mc) % mc), DIM == 3 ? (int)(gc / ((long)mc * mc)) : 1};
-    bool bnd = false;
-    for (int d = 0; d < DIM; ++d) bnd = bnd || K[d] == 0 || K[d] == mc - 1;
-    if (bnd) {
-      a.out[gc] = T(0);
-      return;
-    }
-    int st[3] = {0, 0, 0}, cn[3] = {1, 1, 1}, cl[3] = {0, 0, 0};
-    for (int d = 0; d < DIM; ++d) {
-      const int cc = K[d] / P, al = K[d] % P;
-      cl[d] = al;
-      if (al != 0) {
-        st[d] = 2 * P * cc + 1;
-        cn[d] = 2 * P - 1;
-      } else {
-        st[d] = 2 * P * (cc - 1) + 1;
-        cn[d] = 4 * P - 1;
-      }
-    }
-    constexpr int nw = 4 * P - 1;
-    const T *wx = a.Wr + cl[0] * nw, *wy = a.Wr + cl[1] * nw, *wz = a.Wr + cl[2] * nw;
+template <typename T, int P, bool RESTRICT, bool ADD>
+struct TransferPass {
+  // output entry g of one pass
+  PMG_INLINE static void node(long g, const PassArgs<T> &a) {
+    const int o0 = (int)(g % a.oe[0]);
+    const long r1 = g / a.oe[0];
+    const int o1 = (int)(r1 % a.oe[1]);
+    const int o2 = (int)(r1 / a.oe[1]);
+    const int o[3] = {o0, o1, o2};
+    const int istr[3] = {1, a.ie[0], a.ie[0] * a.ie[1]};
+    const int ax = a.ax;
+    long base = 0;
+    for (int d = 0; d < 3; ++d)
+      if (d != ax) base += (long)o[d] * istr[d];
+    const long st = istr[ax];
+    const cptr<T> W1 = as_const(a.W1), Wr = as_const(a.Wr);
+    const int K = o[ax];
     T acc = 0;
-    for (int tz = 0; tz < cn[2]; ++tz) {
-      const T fz = DIM == 3 ? wz[tz] : T(1);
-      const long bz = DIM == 3 ? (long)(st[2] + tz) * mf * mf : 0;
-      for (int ty = 0; ty < cn[1]; ++ty) {
-        const T fy = fz * wy[ty];
-        const long by = bz + (long)(st[1] + ty) * mf;
-        T s = 0;
-        for (int tx = 0; tx < cn[0]; ++tx) s += wx[tx] * a.in[by + st[0] + tx];
-        acc += fy * s;
+    if (RESTRICT) {
+      const int mc = P * a.nc + 1;
+      if (K > 0 && K < mc - 1) {  // coarse boundary rows vanish
+        const int cc = K / P, cl = K % P;
+        const int first = cl != 0 ? 2 * P * cc + 1 : 2 * P * (cc - 1) + 1;
+        const int cnt = cl != 0 ? 2 * P - 1 : 4 * P - 1;
+        const int nw = 4 * P - 1;
+        for (int t = 0; t < cnt; ++t) acc += Wr[cl * nw + t] * a.in[base + (long)(first + t) * st];
       }
-    }
-    a.out[gc] = acc;
-  }
-
-  // fine node index gf: out[gf] += sum_coarse W1 in[coarse]  (fine boundary untouched)
-  PMG_INLINE static void prolong_node(long gf, const TransferArgs<T> &a) {
-    const int mc = P * a.nc + 1, mf = 2 * P * a.nc + 1;
-    int F[3] = {(int)(gf % mf), (int)((gf / mf) % mf), DIM == 3 ? (int)(gf / ((long)mf * mf)) : 0};
-    for (int d = 0; d < DIM; ++d)
-      if (F[d] == 0 || F[d] == mf - 1) return;
-    int cb[3] = {0, 0, 0}, al[3] = {0, 0, 0};
-    for (int d = 0; d < DIM; ++d) {
-      int cc = F[d] / (2 * P);
-      if (cc > a.nc - 1) cc = a.nc - 1;
-      cb[d] = P * cc;
-      al[d] = F[d] - 2 * P * cc;
-    }
-    const T *wx = a.W1 + al[0] * (P + 1), *wy = a.W1 + al[1] * (P + 1), *wz = a.W1 + al[2] * (P + 1);
-    T acc = 0;
-    const int nz = DIM == 3 ? P + 1 : 1;
-    for (int cz = 0; cz < nz; ++cz) {
-      const int Kz = cb[2] + cz;
-      if (DIM == 3 && (Kz == 0 || Kz == mc - 1)) continue;
-      const T fz = DIM == 3 ? wz[cz] : T(1);
-      for (int cy = 0; cy <= P; ++cy) {
-        const int Ky = cb[1] + cy;
-        if (Ky == 0 || Ky == mc - 1) continue;
-        const T fy = fz * wy[cy];
-        const long base = (long)Ky * mc + (DIM == 3 ? (long)Kz * mc * mc : 0);
-        T s = 0;
-        for (int cx = 0; cx <= P; ++cx) {
-          const int Kx = cb[0] + cx;
-          if (Kx == 0 || Kx == mc - 1) continue;
-          s += wx[cx] * a.in[base + Kx];
+    } else {
+      const int mf = 2 * P * a.nc + 1, mc = P * a.nc + 1;
+      if (K > 0 && K < mf - 1) {  // fine boundary rows vanish
+        int cc = K / (2 * P);
+        if (cc > a.nc - 1) cc = a.nc - 1;
+        const int al = K - 2 * P * cc;
+        for (int c = 0; c <= P; ++c) {
+          const int Kc = P * cc + c;
+          if (Kc > 0 && Kc < mc - 1) acc += W1[al * (P + 1) + c] * a.in[base + (long)Kc * st];
         }
-        acc += fy * s;
       }
     }
-    a.out[gf] += acc;
+    if (ADD)
+      a.out[g] += acc;
+    else
+      a.out[g] = acc;
   }
 };
+
+// Pass schedule of a transfer: restriction contracts x, y, z (fine -> coarse extent);
+// prolongation expands x, y, z and adds the last pass into the fine vector.
+template <typename T>
+PMG_INLINE int transfer_passes(int dim, int P, bool restrict_, const TransferArgs<T> &t, PassArgs<T> pa[3]) {
+  const int mc = P * t.nc + 1, mf = 2 * P * t.nc + 1;
+  int cur[3] = {restrict_ ? mf : mc, restrict_ ? mf : mc, dim == 3 ? (restrict_ ? mf : mc) : 1};
+  const int target = restrict_ ? mc : mf;
+  const T *src = t.in;
+  for (int ax = 0; ax < dim; ++ax) {
+    PassArgs<T> &p = pa[ax];
+    p.W1 = t.W1;
+    p.Wr = t.Wr;
+    p.nc = t.nc;
+    p.ax = ax;
+    for (int d = 0; d < 3; ++d) p.ie[d] = cur[d];
+    cur[ax] = target;
+    for (int d = 0; d < 3; ++d) p.oe[d] = cur[d];
+    p.in = src;
+    p.out = ax == dim - 1 ? t.out : (ax % 2 == 0 ? t.w1 : t.w2);
+    src = p.out;
+  }
+  return dim;
+}
 
 // ---------------------------------------------------------------------------------------
 // Coarsest mesh: z = A_0^{-1} r by fast diagonalization of the Cartesian interior operator,

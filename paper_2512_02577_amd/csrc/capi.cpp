@@ -50,7 +50,8 @@ int fail(int code, const char *fmt, ...) {
 template <typename T>
 struct PrecData {
   DevTabs<T> tabs{};
-  std::vector<T *> r, z, t;  // per h-level work vectors
+  std::vector<T *> r, z, t;   // per h-level work vectors
+  T *tw1 = nullptr, *tw2 = nullptr;  // intermediates of the 1D transfer passes
 };
 
 }  // namespace
@@ -174,6 +175,8 @@ int do_restrict(pmg_problem *pr, int l, const T *fine, T *coarse, hipStream_t s)
   a.nc = pr->sizes[l - 1];
   a.in = fine;
   a.out = coarse;
+  a.w1 = pr->pd<T>().tw1;
+  a.w2 = pr->pd<T>().tw2;
   PMG_TRY(launch_restrict<T>(pr->dim, pr->p, a, s));
   return PMG_OK;
 }
@@ -186,6 +189,8 @@ int do_prolong(pmg_problem *pr, int l, const T *coarse, T *fine, hipStream_t s) 
   a.nc = pr->sizes[l - 1];
   a.in = coarse;
   a.out = fine;
+  a.w1 = pr->pd<T>().tw1;
+  a.w2 = pr->pd<T>().tw2;
   PMG_TRY(launch_prolong_add<T>(pr->dim, pr->p, a, s));
   return PMG_OK;
 }
@@ -527,6 +532,14 @@ int pmg_device_init(pmg_problem *pr) {
     if (l >= 1 && (rc = dev_alloc(pr, &pr->d64.t[l], N))) return bail(rc);
     if ((rc = dev_alloc(pr, &pr->d32.r[l], N)) || (rc = dev_alloc(pr, &pr->d32.z[l], N))) return bail(rc);
     if (l >= 1 && (rc = dev_alloc(pr, &pr->d32.t[l], N))) return bail(rc);
+  }
+  // transfer intermediates, sized by the finest pair of levels
+  if (nh > 1) {
+    const size_t mf = (size_t)pr->p * pr->sizes[nh - 1] + 1, mc = (size_t)pr->p * pr->sizes[nh - 2] + 1;
+    const size_t w = pr->dim == 3 ? mf * mf * mc : mf * mc;
+    if ((rc = dev_alloc(pr, &pr->d64.tw1, w)) || (rc = dev_alloc(pr, &pr->d64.tw2, w)) ||
+        (rc = dev_alloc(pr, &pr->d32.tw1, w)) || (rc = dev_alloc(pr, &pr->d32.tw2, w)))
+      return bail(rc);
   }
   // outer solver vectors
   const size_t NF = (size_t)pr->nodes(nh - 1);

@@ -102,13 +102,18 @@ struct EmuTransfer {
   template <int P>
   struct F {
     static int run(const TransferArgs<double> &a) {
-      const int nc = a.nc;
-      if (RESTRICT) {
-        long mc = P * nc + 1, tot = DIM == 3 ? mc * mc * mc : mc * mc;
-        for (long g = 0; g < tot; ++g) TransferBody<DIM, double, P>::restrict_node(g, a);
-      } else {
-        long mf = 2 * P * nc + 1, tot = DIM == 3 ? mf * mf * mf : mf * mf;
-        for (long g = 0; g < tot; ++g) TransferBody<DIM, double, P>::prolong_node(g, a);
+      PassArgs<double> pa[3];
+      const int np = transfer_passes<double>(DIM, P, RESTRICT, a, pa);
+      for (int k = 0; k < np; ++k) {
+        const long total = (long)pa[k].oe[0] * pa[k].oe[1] * pa[k].oe[2];
+        for (long g = 0; g < total; ++g) {
+          if (RESTRICT)
+            TransferPass<double, P, true, false>::node(g, pa[k]);
+          else if (k == np - 1)
+            TransferPass<double, P, false, true>::node(g, pa[k]);
+          else
+            TransferPass<double, P, false, false>::node(g, pa[k]);
+        }
       }
       return 0;
     }
@@ -183,6 +188,10 @@ int pmgemu_transfer(int dim, int nc, int p, int restrict_, const double *in, dou
   a.nc = nc;
   a.in = in;
   a.out = out;
+  const long mc = (long)p * nc + 1, mf = 2L * p * nc + 1;
+  std::vector<double> w1((size_t)(dim == 3 ? mc * mf * mf : mc * mf)), w2((size_t)(dim == 3 ? mf * mf * mc : 1));
+  a.w1 = w1.data();
+  a.w2 = w2.data();
   if (dim == 3)
     return restrict_ ? dispatch_degree<EmuTransfer<3, true>::F>(p, a) : dispatch_degree<EmuTransfer<3, false>::F>(p, a);
   return restrict_ ? dispatch_degree<EmuTransfer<2, true>::F>(p, a) : dispatch_degree<EmuTransfer<2, false>::F>(p, a);

@@ -12,55 +12,70 @@ namespace pmg {
 
 namespace detail {
 
+// Each workgroup kernel comes in two variants: the arena in LDS (dynamic shared memory,
+// so every arena access compiles to ds_read/ds_write), or, when the arena exceeds the
+// device's LDS limit, a slice of a global buffer with a grid-stride loop.
 template <typename T>
-__device__ inline T *arena_ptr(void *global, size_t elems) {
+__device__ inline T *lds_arena() {
   extern __shared__ __align__(16) unsigned char smem[];
-  if (global) return reinterpret_cast<T *>(global) + (size_t)blockIdx.x * elems;
   return reinterpret_cast<T *>(smem);
 }
 
 // ---- patch smoother: one workgroup per patch of one color ----
 template <int DIM, typename T, int P, class H>
-__global__ __launch_bounds__(patch_threads(P)) void k_smooth(SmoothArgs<T> a, void *garena) {
+__global__ __launch_bounds__(patch_threads(P)) void k_smooth(SmoothArgs<T> a) {
   using B = PatchBody<DIM, T, patch_threads(P), P, H>;
-  T *lds = arena_ptr<T>(garena, B::size);
+  B::smooth_patch(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+}
+
+template <int DIM, typename T, int P, class H>
+__global__ __launch_bounds__(patch_threads(P)) void k_smooth_g(SmoothArgs<T> a, void *garena) {
+  using B = PatchBody<DIM, T, patch_threads(P), P, H>;
+  T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
   for (int blk = blockIdx.x; blk < a.n_patch; blk += gridDim.x) {
-    B::smooth_patch(threadIdx.x, blk, lds, a);
+    B::smooth_patch(threadIdx.x, blk, ar, a);
     __syncthreads();
   }
 }
 
 template <int DIM, typename T, int P, class H>
-__global__ __launch_bounds__(patch_threads(P)) void k_local(SmoothArgs<T> a, int n_blocks, void *garena) {
+__global__ __launch_bounds__(patch_threads(P)) void k_local(SmoothArgs<T> a, int n_blocks) {
   using B = PatchBody<DIM, T, patch_threads(P), P, H>;
-  T *lds = arena_ptr<T>(garena, B::size);
+  B::local_only(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+}
+
+template <int DIM, typename T, int P, class H>
+__global__ __launch_bounds__(patch_threads(P)) void k_local_g(SmoothArgs<T> a, int n_blocks, void *garena) {
+  using B = PatchBody<DIM, T, patch_threads(P), P, H>;
+  T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
   for (int blk = blockIdx.x; blk < n_blocks; blk += gridDim.x) {
-    B::local_only(threadIdx.x, blk, lds, a);
+    B::local_only(threadIdx.x, blk, ar, a);
     __syncthreads();
   }
 }
 
 // ---- operator apply: one workgroup per tile ----
 template <int DIM, typename T, int P, bool RESID>
-__global__ __launch_bounds__(apply_threads(P)) void k_apply(ApplyArgs<T> a, void *garena) {
+__global__ __launch_bounds__(apply_threads(P)) void k_apply(ApplyArgs<T> a) {
   using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID>;
-  T *lds = arena_ptr<T>(garena, B::size);
+  B::run(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+}
+
+template <int DIM, typename T, int P, bool RESID>
+__global__ __launch_bounds__(apply_threads(P)) void k_apply_g(ApplyArgs<T> a, void *garena) {
+  using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID>;
+  T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
   for (int blk = blockIdx.x; blk < a.n_tiles; blk += gridDim.x) {
-    B::run(threadIdx.x, blk, lds, a);
+    B::run(threadIdx.x, blk, ar, a);
     __syncthreads();
   }
 }
 
-template <int DIM, typename T, int P>
-__global__ __launch_bounds__(256) void k_restrict(TransferArgs<T> a, long total) {
+// ---- h-transfer: one 1D pass, one thread per output entry ----
+template <typename T, int P, bool RESTRICT, bool ADD>
+__global__ __launch_bounds__(256) void k_transfer(PassArgs<T> a, long total) {
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < total) TransferBody<DIM, T, P>::restrict_node(g, a);
-}
-
-template <int DIM, typename T, int P>
-__global__ __launch_bounds__(256) void k_prolong(TransferArgs<T> a, long total) {
-  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < total) TransferBody<DIM, T, P>::prolong_node(g, a);
+  if (g < total) TransferPass<T, P, RESTRICT, ADD>::node(g, a);
 }
 
 template <int DIM, typename T>
@@ -68,28 +83,28 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
   CoarseBody<DIM, T, 256>::run(threadIdx.x, a);
 }
 
-// Launch with `bytes` of dynamic LDS (or the global arena when it does not fit).
-template <typename K, typename... Args>
-int launch_arena(K kernel, int nblk, int threads, size_t bytes, const Arena &ar, hipStream_t s, Args... args) {
+// Launch the LDS variant with `bytes` of dynamic shared memory, or the global-arena
+// variant (grid capped at the arena's slots) when the arena does not fit in LDS.
+template <typename KL, typename KG, typename... Args>
+int launch_arena(KL klds, KG kglob, int nblk, int threads, size_t bytes, const Arena &ar, hipStream_t s,
+                 Args... args) {
   if (nblk <= 0) return 0;
-  void *g = nullptr;
-  size_t shmem = bytes;
-  int grid = nblk;
   if (bytes > ar.lds_max) {
     if (!ar.global || ar.slots <= 0) return -3;
-    g = ar.global;
-    shmem = 0;
-    grid = nblk < ar.slots ? nblk : ar.slots;
-  } else if (bytes > 65536) {
-    static thread_local const void *last = nullptr;
-    if (last != (const void *)kernel) {
-      if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
-          hipSuccess)
-        return -4;
-      last = (const void *)kernel;
+    const int grid = nblk < ar.slots ? nblk : ar.slots;
+    hipLaunchKernelGGL(kglob, dim3(grid), dim3(threads), 0, s, args..., ar.global);
+  } else {
+    if (bytes > 65536) {
+      static thread_local const void *last = nullptr;
+      if (last != (const void *)klds) {
+        if (hipFuncSetAttribute((const void *)klds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+            hipSuccess)
+          return -4;
+        last = (const void *)klds;
+      }
     }
+    hipLaunchKernelGGL(klds, dim3(nblk), dim3(threads), bytes, s, args...);
   }
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), shmem, s, args..., g);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
@@ -101,7 +116,8 @@ struct SmoothL {
     struct F {
       static int run(const SmoothArgs<T> &a, const Arena &ar, hipStream_t s) {
         using B = PatchBody<DIM, T, patch_threads(P), P, H>;
-        return launch_arena(k_smooth<DIM, T, P, H>, a.n_patch, patch_threads(P), B::size * sizeof(T), ar, s, a);
+        return launch_arena(k_smooth<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, patch_threads(P),
+                            B::size * sizeof(T), ar, s, a);
       }
     };
   };
@@ -115,7 +131,8 @@ struct LocalL {
     struct F {
       static int run(const SmoothArgs<T> &a, int nb, const Arena &ar, hipStream_t s) {
         using B = PatchBody<DIM, T, patch_threads(P), P, H>;
-        return launch_arena(k_local<DIM, T, P, H>, nb, patch_threads(P), B::size * sizeof(T), ar, s, a, nb);
+        return launch_arena(k_local<DIM, T, P, H>, k_local_g<DIM, T, P, H>, nb, patch_threads(P),
+                            B::size * sizeof(T), ar, s, a, nb);
       }
     };
   };
@@ -149,7 +166,8 @@ struct ApplyL {
   struct F {
     static int run(const ApplyArgs<T> &a, const Arena &ar, hipStream_t s) {
       using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID>;
-      return launch_arena(k_apply<DIM, T, P, RESID>, a.n_tiles, apply_threads(P), B::size * sizeof(T), ar, s, a);
+      return launch_arena(k_apply<DIM, T, P, RESID>, k_apply_g<DIM, T, P, RESID>, a.n_tiles, apply_threads(P),
+                          B::size * sizeof(T), ar, s, a);
     }
   };
 };
@@ -159,14 +177,20 @@ struct TransferL {
   template <int P>
   struct F {
     static int run(const TransferArgs<T> &a, hipStream_t s) {
-      long m = RESTRICT ? (long)P * a.nc + 1 : 2L * P * a.nc + 1;
-      long total = DIM == 3 ? m * m * m : m * m;
-      int grid = (int)((total + 255) / 256);
-      if (RESTRICT)
-        hipLaunchKernelGGL((k_restrict<DIM, T, P>), dim3(grid), dim3(256), 0, s, a, total);
-      else
-        hipLaunchKernelGGL((k_prolong<DIM, T, P>), dim3(grid), dim3(256), 0, s, a, total);
-      return hipGetLastError() == hipSuccess ? 0 : -4;
+      PassArgs<T> pa[3];
+      const int np = transfer_passes<T>(DIM, P, RESTRICT, a, pa);
+      for (int k = 0; k < np; ++k) {
+        const long total = (long)pa[k].oe[0] * pa[k].oe[1] * pa[k].oe[2];
+        const int grid = (int)((total + 255) / 256);
+        if (RESTRICT)
+          hipLaunchKernelGGL((k_transfer<T, P, true, false>), dim3(grid), dim3(256), 0, s, pa[k], total);
+        else if (k == np - 1)
+          hipLaunchKernelGGL((k_transfer<T, P, false, true>), dim3(grid), dim3(256), 0, s, pa[k], total);
+        else
+          hipLaunchKernelGGL((k_transfer<T, P, false, false>), dim3(grid), dim3(256), 0, s, pa[k], total);
+        if (hipGetLastError() != hipSuccess) return -4;
+      }
+      return 0;
     }
   };
 };

@@ -23,11 +23,23 @@
 
 #if defined(__HIP_DEVICE_COMPILE__)
 #define PMG_SYNC() __syncthreads()
+// Operator tables are read through the constant address space: wave-uniform addresses
+// then become scalar loads into SGPRs instead of per-lane vector loads.
+#define PMG_CONST_AS __attribute__((address_space(4)))
 #else
 #define PMG_SYNC() ((void)0)
+#define PMG_CONST_AS
 #endif
 
 namespace pmg {
+
+template <typename T>
+using cptr = const PMG_CONST_AS T *;
+
+template <typename T>
+PMG_INLINE cptr<T> as_const(const T *p) {
+  return (cptr<T>)p;
+}
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -94,9 +106,9 @@ struct Axis {
 
 // oa = A in, ob = B in  (same pattern)
 template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
-PMG_INLINE void contract2(int tid, const T *in, T *oa, const T *__restrict__ A, T *ob,
-                          const T *__restrict__ B) {
+PMG_INLINE void contract2(int tid, const T *in, T *oa, const T *A_, T *ob, const T *B_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
+  const cptr<T> A = as_const(A_), B = as_const(B_);
   static_assert(X::NIN == Pat::nin, "extent mismatch");
   for (int pen = tid; pen < X::NPEN; pen += NT) {
     int ib, obs;
@@ -121,9 +133,9 @@ PMG_INLINE void contract2(int tid, const T *in, T *oa, const T *__restrict__ A, 
 
 // oc = M ia, og = K ia + M ib
 template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
-PMG_INLINE void contract_pair(int tid, const T *ia, const T *ib_, T *oc, T *og,
-                              const T *__restrict__ M, const T *__restrict__ K) {
+PMG_INLINE void contract_pair(int tid, const T *ia, const T *ib_, T *oc, T *og, const T *M_, const T *K_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
+  const cptr<T> M = as_const(M_), K = as_const(K_);
   static_assert(X::NIN == Pat::nin, "extent mismatch");
   for (int pen = tid; pen < X::NPEN; pen += NT) {
     int ib, obs;
@@ -152,9 +164,10 @@ PMG_INLINE void contract_pair(int tid, const T *ia, const T *ib_, T *oc, T *og,
 
 // out = base - s (K ia + M ib)   (base != nullptr), or out = s (K ia + M ib)
 template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
-PMG_INLINE void contract_final(int tid, const T *ia, const T *ib_, T *out, const T *base, T s,
-                               const T *__restrict__ K, const T *__restrict__ M) {
+PMG_INLINE void contract_final(int tid, const T *ia, const T *ib_, T *out, const T *base, T s, const T *K_,
+                               const T *M_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
+  const cptr<T> K = as_const(K_), M = as_const(M_);
   static_assert(X::NIN == Pat::nin, "extent mismatch");
   for (int pen = tid; pen < X::NPEN; pen += NT) {
     int ib, obs;
@@ -179,8 +192,9 @@ PMG_INLINE void contract_final(int tid, const T *ia, const T *ib_, T *out, const
 
 // out = Mat in  (ADD: out += Mat in)
 template <int AX, int E0, int E1, int E2, class Pat, int NT, bool ADD, typename T>
-PMG_INLINE void contract1(int tid, const T *in, T *out, const T *__restrict__ Mat) {
+PMG_INLINE void contract1(int tid, const T *in, T *out, const T *Mat_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
+  const cptr<T> Mat = as_const(Mat_);
   static_assert(X::NIN == Pat::nin, "extent mismatch");
   for (int pen = tid; pen < X::NPEN; pen += NT) {
     int ib, obs;
