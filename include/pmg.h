@@ -53,8 +53,11 @@ enum {
   PMG_ERR_STATE = -7
 };
 
-/* Arithmetic of a call: vectors and computation in float64 or float32. */
-enum { PMG_FP64 = 0, PMG_FP32 = 1 };
+/* Arithmetic of a call: vectors and computation in float64 or float32.  PMG_FP32_BF16
+ * computes in float32 with float32 vectors but reads the stored operator data of the
+ * general path (per-Gauss-point metric, per-patch inverse diagonals) in bfloat16; on the
+ * Cartesian path there is no stored operator data and it equals PMG_FP32. */
+enum { PMG_FP64 = 0, PMG_FP32 = 1, PMG_FP32_BF16 = 2 };
 
 /* Local patch solver (Sec. 2.2): one half V-cycle (no post-smoothing, Sec. 2.2.1) or a
  * full V-cycle per Richardson step. */
@@ -92,9 +95,12 @@ void pmg_default_config(pmg_config *cfg);
  *   n         cells per direction on the finest mesh, 2 <= n <= 1024.
  *   n_hlevels number of h-levels, or 0: halve n while it is even and above 3.
  *   vertices  NULL for the uniform Cartesian unit box.  Otherwise host array of
- *             (n+1)^dim * dim doubles (vertex-major, x fastest) of a distorted mesh; the
- *             general-geometry path is not built yet and such calls return
- *             PMG_ERR_UNSUPPORTED.
+ *             (n+1)^dim * dim doubles (vertex-major, x fastest) of a distorted mesh (Sec. 4
+ *             moves interior vertices of a Cartesian grid); every cell is the multilinear
+ *             image of the reference cell, coarser levels take the fine vertices at their
+ *             stride (topological nesting, Sec. 2).  Such meshes use the general path:
+ *             the metric w mu |det J| J^-1 J^-T is stored per Gauss point and the patch
+ *             diagonals per patch.
  * The mesh owns a copy of everything it needs; *out is set on success only. */
 int pmg_setup_mesh(int dim, int n, int n_hlevels, const double *vertices, pmg_mesh **out);
 
@@ -131,8 +137,23 @@ int pmg_problem_sizes(const pmg_problem *pr, int *dim, int *n_hlevels, int *n_pl
 int pmg_export_maps(const pmg_problem *pr, int hlevel, int plevel, int32_t *cell_dofs,
                     int32_t *patch_interior, int32_t *patch_closure, uint8_t *patch_color);
 
+/* Physical Gauss points of h-level `hlevel` at the degree of p-level `plevel`:
+ * n_l^dim cells x (q+1)^dim points x dim doubles (cells and points lexicographic, x
+ * fastest), into a caller-owned host array.  Used to evaluate a coefficient. */
+int pmg_get_qpoints(const pmg_problem *pr, int hlevel, int plevel, double *xyz);
+
+/* Coefficient mu of the bilinear form (Sec. 3: mu at quadrature points) on h-level
+ * `hlevel`, p-level `plevel`: host array with one positive value per Gauss point in the
+ * layout of pmg_get_qpoints (NULL restores mu = 1).  The library copies it.  Every level
+ * is rediscretized with its own values (Sec. 2).  Must precede pmg_device_init; a problem
+ * with a coefficient uses the general path. */
+int pmg_set_coefficient(pmg_problem *pr, int hlevel, int plevel, const double *a_q);
+
 /* Uploads the operator tables and allocates every device workspace on the current HIP
- * device.  Must be called once before any entry point below. */
+ * device.  Must be called once before any entry point below.  On the general path it
+ * also computes the metric of every level, the per-patch inverse diagonals (on the
+ * device, from element diagonals) and the dense inverse of the coarsest interior operator
+ * (Cholesky on the device). */
 int pmg_device_init(pmg_problem *pr);
 
 /* v = A_l u on h-level `hlevel` (eq. matrix): matrix-free sum-factorized apply of the
@@ -168,7 +189,8 @@ int pmg_prolongate_add(pmg_problem *pr, int hlevel, int prec, const void *coarse
                        void *stream);
 
 /* Exact solve on the coarsest mesh: z = A_0^{-1} r (interior, computed in float64 for
- * either precision), z_i = r_i on boundary nodes. */
+ * either precision), z_i = r_i on boundary nodes.  Cartesian path: fast diagonalization;
+ * general path: the stored dense inverse. */
 int pmg_coarse_solve(pmg_problem *pr, int prec, const void *r, void *z, void *stream);
 
 /* One h-multigrid V(n_pre, n_post) cycle from a zero guess on the finest level:

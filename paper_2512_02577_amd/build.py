@@ -22,8 +22,10 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpmg.so")
 EMU = os.path.join(PKG, "libpmg_hostemu.so")
 
-HIP_SOURCES = ["kernels_3d_f64.hip", "kernels_3d_f32.hip", "kernels_2d_f64.hip", "kernels_2d_f32.hip",
-               "blas.hip", "capi.cpp", "kernels_dispatch.cpp", "host_tables.cpp"]
+HIP_SOURCES = ["kernels_metric_3d_f32.hip", "kernels_metric_3d_bf16.hip", "kernels_metric_3d_f64.hip",
+               "kernels_metric_2d_f64.hip", "kernels_metric_2d_f32.hip",
+               "kernels_3d_f64.hip", "kernels_3d_f32.hip", "kernels_2d_f64.hip", "kernels_2d_f32.hip",
+               "setup.hip", "blas.hip", "capi.cpp", "kernels_dispatch.cpp", "host_tables.cpp", "geometry.cpp"]
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
                # no packed FP32 instructions anywhere in the device code
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -50,27 +52,28 @@ def build_hip(jobs: int = 8) -> str:
     cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".cpp") and src != "host_tables.cpp" else []
+        lang = ["-x", "hip"] if src in ("capi.cpp", "kernels_dispatch.cpp") else []
         cmds.append([hipcc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(cmds)))) as ex:
         list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lhipsolver",
+          "-lpthread", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 
 
 def build_emulation(asan: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [os.path.join(CSRC, "hostemu.cpp"), os.path.join(CSRC, "host_tables.cpp")]
+    srcs = [os.path.join(CSRC, "hostemu.cpp"), os.path.join(CSRC, "host_tables.cpp"), os.path.join(CSRC, "geometry.cpp")]
     tmp = EMU + ".tmp"
-    _run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I" + CSRC, *srcs, "-o", tmp])
+    _run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I" + CSRC, *srcs, "-o", tmp, "-lpthread"])
     os.replace(tmp, EMU)
     if asan:
         exe = os.path.join(BUILD, "hostemu_asan")
         _run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
-              "-I" + CSRC, os.path.join(CSRC, "hostemu_check.cpp"), *srcs, "-o", exe])
+              "-I" + CSRC, os.path.join(CSRC, "hostemu_check.cpp"), *srcs, "-o", exe, "-lpthread"])
         return exe
     return EMU
 

@@ -9,9 +9,13 @@
 #include <cstring>
 #include <exception>
 #include <string>
+#include <type_traits>
 #include <vector>
 
+#include <hipsolver/hipsolver.h>
+
 #include "dispatch.h"
+#include "geometry.h"
 #include "host_tables.h"
 #include "launch.h"
 #include "pmg.h"
@@ -58,7 +62,8 @@ struct PrecData {
 
 struct pmg_mesh {
   int dim = 3, n = 0;
-  std::vector<int> sizes;  // cells per direction, coarsest first
+  std::vector<int> sizes;   // cells per direction, coarsest first
+  std::vector<double> verts;  // finest-level vertices, empty for the Cartesian unit box
 };
 
 struct pmg_problem {
@@ -76,7 +81,20 @@ struct pmg_problem {
   double *fr[2] = {nullptr, nullptr}, *fz = nullptr, *fp = nullptr, *fq = nullptr;
   double *part = nullptr, *scal = nullptr, *hscal = nullptr;
   Arena arena;
+  // general path (distorted vertices or a coefficient): per (h-level, p-level) data
+  bool general = false;
+  std::vector<dvec> verts;                  // per h-level
+  std::vector<dvec> coef;                   // [hl * L + pl], empty = mu 1
+  std::vector<QTabDev<double>> qt64;        // per p-level
+  std::vector<QTabDev<float>> qt32;
+  std::vector<const double *> G64, invD64;  // [hl * L + pl]
+  std::vector<const float *> G32, invD32;
+  std::vector<const bf16 *> G16, invD16;
+  double *Ainv = nullptr, *cwork = nullptr; // dense coarse inverse and its gather vector
+  int coarse_mi = 0;
 
+  int nplev() const { return (int)degrees.size(); }
+  long cells(int l) const { return dim == 3 ? (long)sizes[l] * sizes[l] * sizes[l] : (long)sizes[l] * sizes[l]; }
   long nodes(int l) const {
     long m = (long)p * sizes[l] + 1;
     return dim == 3 ? m * m * m : m * m;
@@ -106,13 +124,155 @@ int check_level(const pmg_problem *pr, int hlevel) {
   return PMG_OK;
 }
 
+// Storage of the general path's stored operator data (metric, patch diagonals):
+// the compute type, or bfloat16 (FP32 compute, 3D only).
+enum Store { ST_NATIVE = 0, ST_BF16 = 1 };
+
 int check_prec(int prec) {
-  if (prec != PMG_FP64 && prec != PMG_FP32) return fail(PMG_ERR_INVALID_ARG, "precision %d unknown", prec);
+  if (prec != PMG_FP64 && prec != PMG_FP32 && prec != PMG_FP32_BF16)
+    return fail(PMG_ERR_INVALID_ARG, "precision %d unknown", prec);
   return PMG_OK;
 }
 
+int store_of(int prec) { return prec == PMG_FP32_BF16 ? ST_BF16 : ST_NATIVE; }
+
 template <typename T>
-int do_apply(pmg_problem *pr, int l, bool resid, const T *b, const T *u, T *out, hipStream_t s) {
+const QTabDev<T> &qtab(pmg_problem *pr, int l);
+template <>
+const QTabDev<double> &qtab<double>(pmg_problem *pr, int l) { return pr->qt64[l]; }
+template <>
+const QTabDev<float> &qtab<float>(pmg_problem *pr, int l) { return pr->qt32[l]; }
+
+template <typename S>
+const S *metric_of(pmg_problem *pr, int hl, int pl);
+template <>
+const double *metric_of<double>(pmg_problem *pr, int hl, int pl) { return pr->G64[hl * pr->nplev() + pl]; }
+template <>
+const float *metric_of<float>(pmg_problem *pr, int hl, int pl) { return pr->G32[hl * pr->nplev() + pl]; }
+template <>
+const bf16 *metric_of<bf16>(pmg_problem *pr, int hl, int pl) { return pr->G16[hl * pr->nplev() + pl]; }
+
+template <typename S>
+const S *invd_of(pmg_problem *pr, int hl, int pl);
+template <>
+const double *invd_of<double>(pmg_problem *pr, int hl, int pl) { return pr->invD64[hl * pr->nplev() + pl]; }
+template <>
+const float *invd_of<float>(pmg_problem *pr, int hl, int pl) { return pr->invD32[hl * pr->nplev() + pl]; }
+template <>
+const bf16 *invd_of<bf16>(pmg_problem *pr, int hl, int pl) { return pr->invD16[hl * pr->nplev() + pl]; }
+
+template <int DIM, typename T, typename S>
+int metric_apply_dim(pmg_problem *pr, int hl, bool resid, const T *b, const T *u, T *out, hipStream_t s) {
+  using ML = MetricLaunchers<DIM, T, S>;
+  const int n = pr->sizes[hl], m = pr->p * n + 1, L = pr->nplev();
+  PMG_TRY(ML::apply_init(m, resid, b, u, out, s));
+  MetricApplyArgs<T, S> a{};
+  a.qt = qtab<T>(pr, L - 1);
+  a.G = metric_of<S>(pr, hl, L - 1);
+  a.n = n;
+  a.sign = resid ? T(-1) : T(1);
+  a.u = u;
+  a.out = out;
+  for (int col = 0; col < (1 << DIM); ++col) {
+    MetricApplyArgs<T, S> c = a;
+    c.n_cells = 1;
+    for (int d = 0; d < 3; ++d) {
+      if (d >= DIM) {
+        c.first[d] = 0;
+        c.cnt[d] = 1;
+        continue;
+      }
+      c.first[d] = (col >> d) & 1;
+      c.cnt[d] = c.first[d] <= n - 1 ? (n - 1 - c.first[d]) / 2 + 1 : 0;
+      c.n_cells *= c.cnt[d];
+    }
+    if (c.n_cells == 0) continue;
+    PMG_TRY(ML::apply(pr->p, c, pr->arena, s));
+  }
+  return PMG_OK;
+}
+
+template <typename T, typename S>
+MetricSmoothArgs<T, S> metric_args(pmg_problem *pr, int hl) {
+  MetricSmoothArgs<T, S> a{};
+  for (int l = 0; l < pr->nplev(); ++l) {
+    a.lev[l].qt = qtab<T>(pr, l);
+    a.lev[l].Tp = pr->pd<T>().tabs.Tp[l];
+    a.lev[l].TpT = pr->pd<T>().tabs.TpT[l];
+    a.lev[l].G = metric_of<S>(pr, hl, l);
+    a.lev[l].invD = invd_of<S>(pr, hl, l);
+  }
+  a.n = pr->sizes[hl];
+  a.full = pr->cfg.local_solver == PMG_LOCAL_FULL_V;
+  a.n_iter = pr->cfg.n_local_iter;
+  return a;
+}
+
+template <int DIM, typename T, typename S>
+int metric_smooth_dim(pmg_problem *pr, int hl, int dir, T *u, const T *b, hipStream_t s) {
+  MetricSmoothArgs<T, S> base = metric_args<T, S>(pr, hl);
+  base.u = u;
+  base.b = b;
+  const int n = pr->sizes[hl], ncol = 1 << DIM;
+  for (int ci = 0; ci < ncol; ++ci) {
+    const int col = dir > 0 ? ci : ncol - 1 - ci;
+    MetricSmoothArgs<T, S> a = base;
+    a.n_patch = 1;
+    for (int d = 0; d < 3; ++d) {
+      if (d >= DIM) {
+        a.first[d] = 0;
+        a.cnt[d] = 1;
+        continue;
+      }
+      a.first[d] = (col >> d) & 1 ? 1 : 2;
+      a.cnt[d] = a.first[d] <= n - 1 ? (n - 1 - a.first[d]) / 2 + 1 : 0;
+      a.n_patch *= a.cnt[d];
+    }
+    if (a.n_patch == 0) continue;
+    PMG_TRY((MetricLaunchers<DIM, T, S>::smooth(pr->p, a, pr->arena, s)));
+  }
+  return PMG_OK;
+}
+
+template <int DIM, typename T, typename S>
+int metric_local_dim(pmg_problem *pr, int hl, int first, int nb, const T *r, T *d, hipStream_t s) {
+  MetricSmoothArgs<T, S> a = metric_args<T, S>(pr, hl);
+  a.r_blocks = r;
+  a.d_blocks = d;
+  a.first_patch = first;
+  PMG_TRY((MetricLaunchers<DIM, T, S>::local(pr->p, a, nb, pr->arena, s)));
+  return PMG_OK;
+}
+
+// runtime (dimension, storage) -> instantiated metric launchers; 2D and FP64 ignore ST_BF16
+#define PMG_METRIC_DISPATCH(FN, T, store, ...)                                     \
+  do {                                                                             \
+    if (pr->dim == 3) {                                                            \
+      if constexpr (std::is_same<T, float>::value)                                 \
+        if (store == ST_BF16) return FN<3, float, bf16>(__VA_ARGS__);              \
+      return FN<3, T, T>(__VA_ARGS__);                                             \
+    }                                                                              \
+    return FN<2, T, T>(__VA_ARGS__);                                               \
+  } while (0)
+
+template <typename T>
+int general_apply(pmg_problem *pr, int hl, bool resid, const T *b, const T *u, T *out, hipStream_t s, int store) {
+  PMG_METRIC_DISPATCH(metric_apply_dim, T, store, pr, hl, resid, b, u, out, s);
+}
+
+template <typename T>
+int general_smooth(pmg_problem *pr, int hl, int dir, T *u, const T *b, hipStream_t s, int store) {
+  PMG_METRIC_DISPATCH(metric_smooth_dim, T, store, pr, hl, dir, u, b, s);
+}
+
+template <typename T>
+int general_local(pmg_problem *pr, int hl, int first, int nb, const T *r, T *d, hipStream_t s, int store) {
+  PMG_METRIC_DISPATCH(metric_local_dim, T, store, pr, hl, first, nb, r, d, s);
+}
+
+template <typename T>
+int do_apply(pmg_problem *pr, int l, bool resid, const T *b, const T *u, T *out, hipStream_t s, int store = ST_NATIVE) {
+  if (pr->general) return general_apply<T>(pr, l, resid, b, u, out, s, store);
   const int tc = tile_cells(pr->p);
   ApplyArgs<T> a{};
   a.Kt = pr->pd<T>().tabs.Kt;
@@ -141,7 +301,8 @@ SmoothArgs<T> smooth_args(pmg_problem *pr, int l) {
 }
 
 template <typename T>
-int do_smooth(pmg_problem *pr, int l, int dir, T *u, const T *b, hipStream_t s) {
+int do_smooth(pmg_problem *pr, int l, int dir, T *u, const T *b, hipStream_t s, int store = ST_NATIVE) {
+  if (pr->general) return general_smooth<T>(pr, l, dir, u, b, s, store);
   SmoothArgs<T> base = smooth_args<T>(pr, l);
   base.u = u;
   base.b = b;
@@ -197,6 +358,10 @@ int do_prolong(pmg_problem *pr, int l, const T *coarse, T *fine, hipStream_t s) 
 
 template <typename T>
 int do_coarse(pmg_problem *pr, const T *r, T *z, hipStream_t s) {
+  if (pr->general) {
+    PMG_TRY(launch_coarse_dense<T>(pr->dim, pr->coarse_mi, pr->coarse_mi + 2, pr->Ainv, r, z, pr->cwork, s));
+    return PMG_OK;
+  }
   CoarseArgs<T> a{};
   a.S = pr->S0;
   a.lam = pr->lam0;
@@ -213,7 +378,7 @@ int do_coarse(pmg_problem *pr, const T *r, T *z, hipStream_t s) {
 
 // h-multigrid V(n_pre, n_post) from a zero guess on the finest level (Sec. 2).
 template <typename T>
-int do_vcycle(pmg_problem *pr, const T *r, T *z, hipStream_t s) {
+int do_vcycle(pmg_problem *pr, const T *r, T *z, hipStream_t s, int store = ST_NATIVE) {
   const int L = pr->finest();
   PrecData<T> &w = pr->pd<T>();
   if (L == 0) return do_coarse<T>(pr, r, z, s);
@@ -223,10 +388,10 @@ int do_vcycle(pmg_problem *pr, const T *r, T *z, hipStream_t s) {
     const int m = pr->p * pr->sizes[l] + 1;
     PMG_TRY(launch_init_z<T>(pr->dim, m, Z, R, s));
     for (int k = 0; k < pr->cfg.n_pre; ++k) {
-      int rc = do_smooth<T>(pr, l, +1, Z, R, s);
+      int rc = do_smooth<T>(pr, l, +1, Z, R, s, store);
       if (rc) return rc;
     }
-    int rc = do_apply<T>(pr, l, true, R, Z, w.t[l], s);
+    int rc = do_apply<T>(pr, l, true, R, Z, w.t[l], s, store);
     if (rc) return rc;
     rc = do_restrict<T>(pr, l, w.t[l], w.r[l - 1], s);
     if (rc) return rc;
@@ -239,7 +404,7 @@ int do_vcycle(pmg_problem *pr, const T *r, T *z, hipStream_t s) {
     rc = do_prolong<T>(pr, l, w.z[l - 1], Z, s);
     if (rc) return rc;
     for (int k = 0; k < pr->cfg.n_post; ++k) {
-      rc = do_smooth<T>(pr, l, -1, Z, R, s);
+      rc = do_smooth<T>(pr, l, -1, Z, R, s, store);
       if (rc) return rc;
     }
   }
@@ -251,7 +416,7 @@ int vcycle_any(pmg_problem *pr, int mg_prec, const double *r, double *z, hipStre
   const int L = pr->finest();
   const long N = pr->nodes(L);
   PMG_TRY(launch_cast_d2f(r, pr->d32.r[L], N, s));
-  int rc = do_vcycle<float>(pr, pr->d32.r[L], pr->d32.z[L], s);
+  int rc = do_vcycle<float>(pr, pr->d32.r[L], pr->d32.z[L], s, mg_prec == PMG_FP32_BF16 ? ST_BF16 : ST_NATIVE);
   if (rc) return rc;
   PMG_TRY(launch_cast_f2d(pr->d32.z[L], z, N, s));
   return PMG_OK;
@@ -314,6 +479,146 @@ void release(pmg_problem *pr) {
   pr->dev = false;
 }
 
+// Device data of the general path: 1D Gauss-point tables per p-level, the metric of every
+// (h-level, p-level) in FP64/FP32/BF16, per-patch inverse diagonals computed on the device
+// from element diagonals, and the dense inverse of the coarsest interior operator.
+int init_general(pmg_problem *pr) {
+  const int L = pr->nplev(), nh = (int)pr->sizes.size(), dim = pr->dim;
+  int rc = PMG_OK;
+  pr->qt64.assign(L, QTabDev<double>{});
+  pr->qt32.assign(L, QTabDev<float>{});
+  std::vector<const double *> B64(L), Dn64(L);
+  for (int l = 0; l < L; ++l) {
+    const QTab t = make_qtab(pr->degrees[l]);
+    const int k = t.q + 1;
+    dvec Dn((size_t)t.nq * k, 0.0);
+    for (int g = 0; g < t.nq; ++g)
+      for (int a = 0; a < k; ++a) {
+        double sum = 0.0;
+        for (int h = 0; h < t.nq; ++h) sum += t.Dq[(size_t)g * t.nq + h] * t.B[(size_t)h * k + a];
+        Dn[(size_t)g * k + a] = sum;
+      }
+    const dvec *parts[] = {&t.B, &t.BT, &t.Dq, &t.DqT, &t.Bpc, &t.Bpi, &t.BpiT, &t.Dqp, &t.DqpT, &Dn};
+    std::vector<double> flat;
+    std::vector<size_t> off;
+    for (const dvec *v : parts) {
+      off.push_back(flat.size());
+      flat.insert(flat.end(), v->begin(), v->end());
+      flat.resize((flat.size() + 31) / 32 * 32 + 32, 0.0);
+    }
+    double *d64;
+    float *d32;
+    if ((rc = dev_alloc(pr, &d64, flat.size())) || (rc = dev_alloc(pr, &d32, flat.size()))) return rc;
+    std::vector<float> flat32(flat.begin(), flat.end());
+    PMG_HIP(hipMemcpy(d64, flat.data(), flat.size() * sizeof(double), hipMemcpyHostToDevice));
+    PMG_HIP(hipMemcpy(d32, flat32.data(), flat32.size() * sizeof(float), hipMemcpyHostToDevice));
+    auto bind = [&](auto &q, auto *base) {
+      q.B = base + off[0]; q.BT = base + off[1]; q.Dq = base + off[2]; q.DqT = base + off[3];
+      q.Bpc = base + off[4]; q.Bpi = base + off[5]; q.BpiT = base + off[6]; q.Dqp = base + off[7];
+      q.DqpT = base + off[8];
+    };
+    bind(pr->qt64[l], d64);
+    bind(pr->qt32[l], d32);
+    B64[l] = d64 + off[0];
+    Dn64[l] = d64 + off[9];
+  }
+  const size_t nslot = (size_t)nh * L;
+  pr->G64.assign(nslot, nullptr);
+  pr->G32.assign(nslot, nullptr);
+  pr->G16.assign(nslot, nullptr);
+  pr->invD64.assign(nslot, nullptr);
+  pr->invD32.assign(nslot, nullptr);
+  pr->invD16.assign(nslot, nullptr);
+  const int nc = metric_components(dim);
+  dvec G;
+  for (int hl = 0; hl < nh; ++hl)
+    for (int l = 0; l < L; ++l) {
+      const int q = pr->degrees[l], n = pr->sizes[hl];
+      const dvec &a = pr->coef[(size_t)hl * L + l];
+      if (!metric(dim, n, pr->verts[hl], q, a.empty() ? nullptr : a.data(), G))
+        return fail(PMG_ERR_INVALID_ARG, "a cell of h-level %d has a non-positive Jacobian determinant", hl);
+      const long npts = pr->cells(hl) * (dim == 3 ? (long)(q + 1) * (q + 1) * (q + 1) : (long)(q + 1) * (q + 1));
+      const size_t ng = (size_t)npts * nc;
+      double *g64;
+      float *g32;
+      bf16 *g16;
+      if ((rc = dev_alloc(pr, &g64, ng)) || (rc = dev_alloc(pr, &g32, ng)) || (rc = dev_alloc(pr, &g16, ng)))
+        return rc;
+      PMG_HIP(hipMemcpy(g64, G.data(), ng * sizeof(double), hipMemcpyHostToDevice));
+      PMG_TRY(launch_convert<float>(g64, g32, (long)ng, nullptr));
+      PMG_TRY(launch_convert<bf16>(g64, g16, (long)ng, nullptr));
+      const size_t slot = (size_t)hl * L + l;
+      pr->G64[slot] = g64;
+      pr->G32[slot] = g32;
+      pr->G16[slot] = g16;
+      // element diagonals -> per-patch inverse diagonals (damping folded in)
+      const long kd = dim == 3 ? (long)(q + 1) * (q + 1) * (q + 1) : (long)(q + 1) * (q + 1);
+      void *cd = nullptr;
+      PMG_HIP(hipMalloc(&cd, (size_t)(pr->cells(hl) * kd) * sizeof(double)));
+      const long e1 = 2 * q - 1, k1 = n - 1;
+      const size_t ni = (size_t)(dim == 3 ? k1 * k1 * k1 * e1 * e1 * e1 : k1 * k1 * e1 * e1);
+      double *i64;
+      float *i32;
+      bf16 *i16;
+      if ((rc = dev_alloc(pr, &i64, ni + 1)) || (rc = dev_alloc(pr, &i32, ni + 1)) || (rc = dev_alloc(pr, &i16, ni + 1))) {
+        (void)hipFree(cd);
+        return rc;
+      }
+      const double om = l == 0 ? 1.0 : pr->tab.omega[l];
+      int krc = launch_cell_diag(dim, q, pr->cells(hl), B64[l], Dn64[l], g64, (double *)cd, nullptr);
+      if (!krc) krc = launch_patch_invdiag<double>(dim, q, n, om, (const double *)cd, i64, nullptr);
+      if (!krc) krc = launch_patch_invdiag<float>(dim, q, n, om, (const double *)cd, i32, nullptr);
+      if (!krc) krc = launch_patch_invdiag<bf16>(dim, q, n, om, (const double *)cd, i16, nullptr);
+      const hipError_t se = hipDeviceSynchronize();
+      (void)hipFree(cd);
+      if (krc || se != hipSuccess) return fail(PMG_ERR_DEVICE, "diagonal setup failed: %s", hipGetErrorString(se));
+      pr->invD64[slot] = i64;
+      pr->invD32[slot] = i32;
+      pr->invD16[slot] = i16;
+    }
+  // coarsest mesh: dense interior operator of degree p -> Cholesky -> inverse
+  {
+    const int n0 = pr->sizes[0], p = pr->p;
+    const int mi = p * n0 - 1;
+    const long m = dim == 3 ? (long)mi * mi * mi : (long)mi * mi;
+    pr->coarse_mi = mi;
+    const int q = p, l = L - 1;
+    const dvec &a = pr->coef[(size_t)0 * L + l];
+    if (!metric(dim, n0, pr->verts[0], q, a.empty() ? nullptr : a.data(), G))
+      return fail(PMG_ERR_INVALID_ARG, "degenerate coarse cell");
+    dvec A;
+    interior_matrix(dim, n0, p, G, A);
+    double *Af;
+    if ((rc = dev_alloc(pr, &Af, (size_t)(m * m))) || (rc = dev_alloc(pr, &pr->Ainv, (size_t)(m * m))) ||
+        (rc = dev_alloc(pr, &pr->cwork, (size_t)m)))
+      return rc;
+    PMG_HIP(hipMemcpy(Af, A.data(), (size_t)(m * m) * sizeof(double), hipMemcpyHostToDevice));
+    PMG_HIP(hipMemset(pr->Ainv, 0, (size_t)(m * m) * sizeof(double)));
+    PMG_TRY(launch_set_identity(pr->Ainv, (int)m, nullptr));
+    hipsolverHandle_t hs;
+    if (hipsolverCreate(&hs) != HIPSOLVER_STATUS_SUCCESS) return fail(PMG_ERR_DEVICE, "hipsolverCreate failed");
+    int lwork = 0, info = -1;
+    int *dinfo = nullptr;
+    double *work = nullptr;
+    bool okf = hipMalloc((void **)&dinfo, sizeof(int)) == hipSuccess;
+    okf = okf && hipsolverDnDpotrf_bufferSize(hs, HIPBLAS_FILL_MODE_LOWER, (int)m, Af, (int)m, &lwork) ==
+                     HIPSOLVER_STATUS_SUCCESS;
+    okf = okf && hipMalloc((void **)&work, (size_t)(lwork > 0 ? lwork : 1) * sizeof(double)) == hipSuccess;
+    okf = okf && hipsolverDnDpotrf(hs, HIPBLAS_FILL_MODE_LOWER, (int)m, Af, (int)m, work, lwork, dinfo) ==
+                     HIPSOLVER_STATUS_SUCCESS;
+    okf = okf && hipMemcpy(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess && info == 0;
+    okf = okf && hipsolverDnDpotrs(hs, HIPBLAS_FILL_MODE_LOWER, (int)m, (int)m, Af, (int)m, pr->Ainv, (int)m, dinfo) ==
+                     HIPSOLVER_STATUS_SUCCESS;
+    okf = okf && hipMemcpy(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess && info == 0;
+    okf = okf && hipDeviceSynchronize() == hipSuccess;
+    if (work) (void)hipFree(work);
+    if (dinfo) (void)hipFree(dinfo);
+    hipsolverDestroy(hs);
+    if (!okf) return fail(PMG_ERR_DEVICE, "coarse Cholesky factorization failed (info %d)", info);
+  }
+  return PMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -337,7 +642,6 @@ int pmg_setup_mesh(int dim, int n, int n_hlevels, const double *vertices, pmg_me
   if (dim != 2 && dim != 3) return fail(PMG_ERR_INVALID_ARG, "dim must be 2 or 3, got %d", dim);
   if (n < 2 || n > 1024) return fail(PMG_ERR_INVALID_ARG, "n must be in [2, 1024], got %d", n);
   if (n_hlevels < 0) return fail(PMG_ERR_INVALID_ARG, "n_hlevels must be >= 0");
-  if (vertices) return fail(PMG_ERR_UNSUPPORTED, "distorted meshes are not supported by this build");
   std::vector<int> sizes{n};
   while (sizes.back() % 2 == 0 && sizes.back() > 3 && (n_hlevels == 0 || (int)sizes.size() < n_hlevels))
     sizes.push_back(sizes.back() / 2);
@@ -348,6 +652,15 @@ int pmg_setup_mesh(int dim, int n, int n_hlevels, const double *vertices, pmg_me
     m->dim = dim;
     m->n = n;
     m->sizes.assign(sizes.rbegin(), sizes.rend());
+    if (vertices) {
+      const size_t nv = dim == 3 ? (size_t)(n + 1) * (n + 1) * (n + 1) : (size_t)(n + 1) * (n + 1);
+      m->verts.assign(vertices, vertices + nv * dim);
+      for (double x : m->verts)
+        if (!std::isfinite(x)) {
+          delete m;
+          return fail(PMG_ERR_INVALID_ARG, "vertex coordinates must be finite");
+        }
+    }
     *out = m;
   } catch (const std::exception &e) {
     return fail(PMG_ERR_OUT_OF_MEMORY, "%s", e.what());
@@ -411,6 +724,11 @@ int pmg_setup_dofmap(const pmg_mesh *m, int degree, const int32_t *p_levels, int
     dvec om;
     if (c.n_omega > 0) om.assign(c.omega, c.omega + c.n_omega);
     build_tables(pr->dim, degree, deg, om, pr->sizes[0], pr->tab);
+    pr->general = !m->verts.empty();
+    for (int l : pr->sizes)
+      pr->verts.push_back(m->verts.empty() ? cartesian_vertices(pr->dim, l)
+                                           : level_vertices(pr->dim, m->n, m->verts, l));
+    pr->coef.assign(pr->sizes.size() * deg.size(), dvec());
     *out = pr;
   } catch (const std::exception &e) {
     return fail(PMG_ERR_INVALID_ARG, "setup failed: %s", e.what());
@@ -476,6 +794,34 @@ int pmg_export_maps(const pmg_problem *pr, int hlevel, int plevel, int32_t *cell
         patch_closure[j * ndc + e] = node(q * (vx - 1) + a, q * (vy - 1) + b, ez ? q * (vz - 1) + f : 0);
       }
   }
+  return PMG_OK;
+}
+
+int pmg_get_qpoints(const pmg_problem *pr, int hlevel, int plevel, double *xyz) {
+  if (!pr || !xyz) return fail(PMG_ERR_INVALID_ARG, "problem or xyz is NULL");
+  if (int rc = check_level(pr, hlevel)) return rc;
+  if (plevel < 0 || plevel >= (int)pr->degrees.size()) return fail(PMG_ERR_INVALID_ARG, "plevel out of range");
+  dvec out;
+  gauss_points(pr->dim, pr->sizes[hlevel], pr->verts[hlevel], pr->degrees[plevel], out);
+  std::memcpy(xyz, out.data(), out.size() * sizeof(double));
+  return PMG_OK;
+}
+
+int pmg_set_coefficient(pmg_problem *pr, int hlevel, int plevel, const double *a_q) {
+  if (!pr) return fail(PMG_ERR_INVALID_ARG, "problem is NULL");
+  if (pr->dev) return fail(PMG_ERR_STATE, "coefficients must be set before pmg_device_init");
+  if (int rc = check_level(pr, hlevel)) return rc;
+  if (plevel < 0 || plevel >= (int)pr->degrees.size()) return fail(PMG_ERR_INVALID_ARG, "plevel out of range");
+  const int q = pr->degrees[plevel];
+  const size_t npts = (size_t)pr->cells(hlevel) * (pr->dim == 3 ? (size_t)(q + 1) * (q + 1) * (q + 1) : (size_t)(q + 1) * (q + 1));
+  dvec &dst = pr->coef[(size_t)hlevel * pr->degrees.size() + plevel];
+  if (!a_q) {
+    dst.clear();
+    return PMG_OK;
+  }
+  for (size_t i = 0; i < npts; ++i)
+    if (!(a_q[i] > 0.0) || !std::isfinite(a_q[i])) return fail(PMG_ERR_INVALID_ARG, "coefficient must be positive and finite");
+  dst.assign(a_q, a_q + npts);
   return PMG_OK;
 }
 
@@ -550,10 +896,16 @@ int pmg_device_init(pmg_problem *pr) {
   if (hipHostMalloc((void **)&pr->hscal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return bail(fail(PMG_ERR_OUT_OF_MEMORY, "pinned scalar buffer"));
   // global arena for kernels whose workgroup arena exceeds the LDS limit
+  pr->general = pr->general || [&]() {
+    for (const dvec &a : pr->coef)
+      if (!a.empty()) return true;
+    return false;
+  }();
+  if (pr->general && pr->hcode != 0) return bail(fail(PMG_ERR_UNSUPPORTED, "the general path compiles the paper's p-hierarchy only"));
   size_t need = 0;
   for (int prec = 0; prec < 2; ++prec) {
-    size_t b1 = patch_arena_bytes(pr->dim, prec, pr->p, pr->hcode);
-    size_t b2 = apply_arena_bytes(pr->dim, prec, pr->p);
+    size_t b1 = pr->general ? metric_patch_arena_bytes(pr->dim, prec, pr->p) : patch_arena_bytes(pr->dim, prec, pr->p, pr->hcode);
+    size_t b2 = pr->general ? metric_apply_arena_bytes(pr->dim, prec, pr->p) : apply_arena_bytes(pr->dim, prec, pr->p);
     if (b1 > pr->arena.lds_max && b1 > need) need = b1;
     if (b2 > pr->arena.lds_max && b2 > need) need = b2;
   }
@@ -563,6 +915,7 @@ int pmg_device_init(pmg_problem *pr) {
     if ((rc = dev_alloc(pr, (unsigned char **)&g, need * pr->arena.slots))) return bail(rc);
     pr->arena.global = g;
   }
+  if (pr->general && (rc = init_general(pr))) return bail(rc);
   pr->dev = true;
   return PMG_OK;
 }
@@ -574,7 +927,7 @@ int pmg_apply_operator(pmg_problem *pr, int hlevel, int prec, const void *u, voi
   if (!u || !v) return fail(PMG_ERR_INVALID_ARG, "u or v is NULL");
   hipStream_t s = (hipStream_t)stream;
   if (prec == PMG_FP64) return do_apply<double>(pr, hlevel, false, nullptr, (const double *)u, (double *)v, s);
-  return do_apply<float>(pr, hlevel, false, nullptr, (const float *)u, (float *)v, s);
+  return do_apply<float>(pr, hlevel, false, nullptr, (const float *)u, (float *)v, s, store_of(prec));
 }
 
 int pmg_residual(pmg_problem *pr, int hlevel, int prec, const void *b, const void *u, void *r, void *stream) {
@@ -584,7 +937,7 @@ int pmg_residual(pmg_problem *pr, int hlevel, int prec, const void *b, const voi
   if (!u || !b || !r) return fail(PMG_ERR_INVALID_ARG, "b, u or r is NULL");
   hipStream_t s = (hipStream_t)stream;
   if (prec == PMG_FP64) return do_apply<double>(pr, hlevel, true, (const double *)b, (const double *)u, (double *)r, s);
-  return do_apply<float>(pr, hlevel, true, (const float *)b, (const float *)u, (float *)r, s);
+  return do_apply<float>(pr, hlevel, true, (const float *)b, (const float *)u, (float *)r, s, store_of(prec));
 }
 
 int pmg_smooth(pmg_problem *pr, int hlevel, int prec, int color_dir, void *u, const void *b, void *stream) {
@@ -595,7 +948,7 @@ int pmg_smooth(pmg_problem *pr, int hlevel, int prec, int color_dir, void *u, co
   if (!u || !b) return fail(PMG_ERR_INVALID_ARG, "u or b is NULL");
   hipStream_t s = (hipStream_t)stream;
   if (prec == PMG_FP64) return do_smooth<double>(pr, hlevel, color_dir, (double *)u, (const double *)b, s);
-  return do_smooth<float>(pr, hlevel, color_dir, (float *)u, (const float *)b, s);
+  return do_smooth<float>(pr, hlevel, color_dir, (float *)u, (const float *)b, s, store_of(prec));
 }
 
 int pmg_local_solve(pmg_problem *pr, int hlevel, int prec, int first_patch, int n_patches, const void *r, void *d,
@@ -609,6 +962,10 @@ int pmg_local_solve(pmg_problem *pr, int hlevel, int prec, int first_patch, int 
   if (n_patches == 0) return PMG_OK;
   if (!r || !d) return fail(PMG_ERR_INVALID_ARG, "r or d is NULL");
   hipStream_t s = (hipStream_t)stream;
+  if (pr->general) {
+    if (prec == PMG_FP64) return general_local<double>(pr, hlevel, first_patch, n_patches, (const double *)r, (double *)d, s, ST_NATIVE);
+    return general_local<float>(pr, hlevel, first_patch, n_patches, (const float *)r, (float *)d, s, store_of(prec));
+  }
   if (prec == PMG_FP64) {
     SmoothArgs<double> a = smooth_args<double>(pr, hlevel);
     a.r_blocks = (const double *)r;

@@ -8,7 +8,9 @@
 #include <cstring>
 #include <vector>
 
+#include "bodies_metric.h"
 #include "dispatch.h"
+#include "geometry.h"
 #include "host_tables.h"
 
 using namespace pmg;
@@ -120,9 +122,159 @@ struct EmuTransfer {
   };
 };
 
+// ---- general path ----
+struct HostQ {
+  QTab t;
+  QTabDev<double> d{};
+  void bind() {
+    d.B = t.B.data(); d.BT = t.BT.data(); d.Dq = t.Dq.data(); d.DqT = t.DqT.data();
+    d.Bpc = t.Bpc.data(); d.Bpi = t.Bpi.data(); d.BpiT = t.BpiT.data(); d.Dqp = t.Dqp.data(); d.DqpT = t.DqpT.data();
+  }
+};
+
+template <int DIM>
+struct EmuMetricApply {
+  template <int P>
+  struct F {
+    static int run(MetricApplyArgs<double, double> base) {
+      using B = MetricApplyBody<DIM, double, double, 1, P>;
+      std::vector<double> lds(B::size);
+      const int ncol = 1 << DIM, n = base.n;
+      for (int col = 0; col < ncol; ++col) {
+        MetricApplyArgs<double, double> a = base;
+        a.n_cells = 1;
+        for (int d = 0; d < 3; ++d) {
+          if (d >= DIM) { a.first[d] = 0; a.cnt[d] = 1; continue; }
+          a.first[d] = (col >> d) & 1;
+          a.cnt[d] = a.first[d] <= n - 1 ? (n - 1 - a.first[d]) / 2 + 1 : 0;
+          a.n_cells *= a.cnt[d];
+        }
+        for (int blk = 0; blk < a.n_cells; ++blk) B::run(0, blk, lds.data(), a);
+      }
+      return 0;
+    }
+  };
+};
+
+template <int DIM>
+struct EmuMetricSmooth {
+  template <int P, class H>
+  struct F {
+    static int run(const MetricSmoothArgs<double, double> &base, int n, int color_dir, bool local_only, int nb) {
+      using B = MetricPatchBody<DIM, double, double, 1, P, H>;
+      std::vector<double> lds(B::size);
+      if (local_only) {
+        for (int blk = 0; blk < nb; ++blk) B::local_only(0, blk, lds.data(), base);
+        return 0;
+      }
+      const int ncol = 1 << DIM;
+      for (int ci = 0; ci < ncol; ++ci) {
+        const int col = color_dir > 0 ? ci : ncol - 1 - ci;
+        MetricSmoothArgs<double, double> a = base;
+        a.n_patch = 1;
+        for (int d = 0; d < 3; ++d) {
+          if (d >= DIM) { a.first[d] = 0; a.cnt[d] = 1; continue; }
+          a.first[d] = (col >> d) & 1 ? 1 : 2;
+          a.cnt[d] = a.first[d] <= n - 1 ? (n - 1 - a.first[d]) / 2 + 1 : 0;
+          a.n_patch *= a.cnt[d];
+        }
+        for (int blk = 0; blk < a.n_patch; ++blk) B::smooth_patch(0, blk, lds.data(), a);
+      }
+      return 0;
+    }
+  };
+};
+
+// per-patch inverse diagonals of one p-level from the metric (host loops over the bodies)
+template <int DIM>
+void emu_inv_diag(int n, int q, double omega, const dvec &G, dvec &invD) {
+  const QTab t = make_qtab(q);
+  const int k = q + 1;
+  dvec Dn((size_t)t.nq * k, 0.0);
+  for (int g = 0; g < t.nq; ++g)
+    for (int a = 0; a < k; ++a) {
+      double s = 0.0;
+      for (int h = 0; h < t.nq; ++h) s += t.Dq[(size_t)g * t.nq + h] * t.B[(size_t)h * k + a];
+      Dn[(size_t)g * k + a] = s;
+    }
+  const long ncell = DIM == 3 ? (long)n * n * n : (long)n * n, kd = DIM == 3 ? k * k * k : k * k;
+  dvec cd((size_t)(ncell * kd));
+  for (long tt = 0; tt < ncell * kd; ++tt) cell_diag<DIM, double>(tt, q, t.B.data(), Dn.data(), G.data(), cd.data());
+  const long e1 = 2 * q - 1, nd = DIM == 3 ? e1 * e1 * e1 : e1 * e1, np = DIM == 3 ? (long)(n - 1) * (n - 1) * (n - 1)
+                                                                                       : (long)(n - 1) * (n - 1);
+  invD.assign((size_t)(np * nd), 0.0);
+  for (long tt = 0; tt < np * nd; ++tt) patch_inv_diag<DIM, double>(tt, q, n, omega, cd.data(), invD.data());
+}
+
 }  // namespace
 
 extern "C" {
+
+// Metric-path apply (resid: out = b - A u) on one level; verts: (n+1)^d x d or NULL for
+// the Cartesian box; coef: per Gauss point of degree p, or NULL.
+int pmgemu_metric_apply(int dim, int n, int p, const double *verts, const double *coef, int resid, const double *u,
+                        const double *b, double *out) {
+  dvec V = verts ? dvec(verts, verts + (size_t)(dim == 3 ? (n + 1) * (n + 1) * (n + 1) : (n + 1) * (n + 1)) * dim)
+                 : cartesian_vertices(dim, n);
+  dvec G;
+  if (!metric(dim, n, V, p, coef, G)) return -1;
+  HostQ hq;
+  hq.t = make_qtab(p);
+  hq.bind();
+  const long m = (long)p * n + 1, N = dim == 3 ? m * m * m : m * m;
+  for (long g = 0; g < N; ++g) metric_apply_init<double>(g, dim, (int)m, resid != 0, b, u, out);
+  MetricApplyArgs<double, double> a{};
+  a.qt = hq.d;
+  a.G = G.data();
+  a.n = n;
+  a.sign = resid ? -1.0 : 1.0;
+  a.u = u;
+  a.out = out;
+  if (dim == 3) return dispatch_degree<EmuMetricApply<3>::F>(p, a);
+  return dispatch_degree<EmuMetricApply<2>::F>(p, a);
+}
+
+// Metric-path smoother (all colors) or local solve (nb > 0: r/d blocks) on one level.
+// coefs: L pointers (Gauss-point coefficient per p-level, NULL entries for mu = 1).
+int pmgemu_metric_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
+                         int color_dir, const double *verts, const double *const *coefs, double *u, const double *b,
+                         int nb, const double *r, double *d) {
+  dvec V = verts ? dvec(verts, verts + (size_t)(dim == 3 ? (n + 1) * (n + 1) * (n + 1) : (n + 1) * (n + 1)) * dim)
+                 : cartesian_vertices(dim, n);
+  Tables tab;
+  std::vector<int> degrees(deg, deg + L);
+  build_tables(dim, p, degrees, dvec(omega, omega + L), n, tab);
+  std::vector<HostQ> hq(L);
+  std::vector<dvec> G(L), invD(L);
+  MetricSmoothArgs<double, double> a{};
+  for (int l = 0; l < L; ++l) {
+    hq[l].t = make_qtab(deg[l]);
+    hq[l].bind();
+    if (!metric(dim, n, V, deg[l], coefs ? coefs[l] : nullptr, G[l])) return -1;
+    if (dim == 3)
+      emu_inv_diag<3>(n, deg[l], l == 0 ? 1.0 : omega[l], G[l], invD[l]);
+    else
+      emu_inv_diag<2>(n, deg[l], l == 0 ? 1.0 : omega[l], G[l], invD[l]);
+    a.lev[l].qt = hq[l].d;
+    a.lev[l].G = G[l].data();
+    a.lev[l].invD = invD[l].data();
+    a.lev[l].Tp = tab.lev[l].Tp.empty() ? nullptr : tab.lev[l].Tp.data();
+    a.lev[l].TpT = tab.lev[l].TpT.empty() ? nullptr : tab.lev[l].TpT.data();
+  }
+  a.n = n;
+  a.full = full;
+  a.n_iter = n_iter;
+  a.u = u;
+  a.b = b;
+  a.r_blocks = r;
+  a.d_blocks = d;
+  const int code = hierarchy_code(p, deg, L);
+  if (code < 0) return -2;
+  if (dim == 3) return dispatch_hierarchy<EmuMetricSmooth<3>::F>(p, code, a, n, color_dir, nb > 0, nb);
+  return dispatch_hierarchy<EmuMetricSmooth<2>::F>(p, code, a, n, color_dir, nb > 0, nb);
+}
+
+
 
 // One smoother application (all colors) on a single Cartesian level of n^dim cells.
 int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,

@@ -13,6 +13,16 @@ size_t apply_arena_bytes(int dim, int prec, int p) {
   return dim == 3 ? Launchers<3, float>::apply_bytes(p) : Launchers<2, float>::apply_bytes(p);
 }
 
+size_t metric_patch_arena_bytes(int dim, int prec, int p) {
+  if (prec == 0) return dim == 3 ? MetricLaunchers<3, double, double>::patch_bytes(p) : MetricLaunchers<2, double, double>::patch_bytes(p);
+  return dim == 3 ? MetricLaunchers<3, float, float>::patch_bytes(p) : MetricLaunchers<2, float, float>::patch_bytes(p);
+}
+
+size_t metric_apply_arena_bytes(int dim, int prec, int p) {
+  if (prec == 0) return dim == 3 ? MetricLaunchers<3, double, double>::apply_bytes(p) : MetricLaunchers<2, double, double>::apply_bytes(p);
+  return dim == 3 ? MetricLaunchers<3, float, float>::apply_bytes(p) : MetricLaunchers<2, float, float>::apply_bytes(p);
+}
+
 template <typename T>
 int launch_smooth_color(int dim, int p, int hcode, const SmoothArgs<T> &a, const Arena &ar, hipStream_t s) {
   return dim == 3 ? Launchers<3, T>::smooth(p, hcode, a, ar, s) : Launchers<2, T>::smooth(p, hcode, a, ar, s);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bodies.h"
+#include "bodies_metric.h"
 
 namespace pmg {
 
@@ -28,9 +29,38 @@ struct Launchers {
   static int coarse(const CoarseArgs<T> &a, hipStream_t s);
 };
 
+// Launchers of the general (metric) path; instantiated in kernels_metric_*.hip for
+// (3D, 2D) x (double/double, float/float) and 3D float/bfloat16.
+template <int DIM, typename T, typename S>
+struct MetricLaunchers {
+  static size_t patch_bytes(int p);
+  static size_t apply_bytes(int p);
+  static int smooth(int p, const MetricSmoothArgs<T, S> &a, const Arena &ar, hipStream_t s);
+  static int local(int p, const MetricSmoothArgs<T, S> &a, int nb, const Arena &ar, hipStream_t s);
+  static int apply(int p, const MetricApplyArgs<T, S> &a, const Arena &ar, hipStream_t s);
+  static int apply_init(int m, bool resid, const T *b, const T *u, T *out, hipStream_t s);
+};
+
+// Setup and coarse-solve kernels of the general path (setup.hip).
+// cdiag[cell * (q+1)^d + node] = diagonal of the element matrix of degree q (metric G, FP64)
+int launch_cell_diag(int dim, int q, long n_cells, const double *B, const double *Dn, const double *G, double *cdiag,
+                     hipStream_t s);
+// invD[patch * (2q-1)^d + e] = omega / (patch diagonal), stored as S
+template <typename S>
+int launch_patch_invdiag(int dim, int q, int n, double omega, const double *cdiag, S *invD, hipStream_t s);
+int launch_set_identity(double *A, int m, hipStream_t s);
+// z = Ainv r on interior nodes of an m0^d interior grid (total nodes per direction mt),
+// z = r on boundary nodes; w is a work vector of m interior entries
+template <typename T>
+int launch_coarse_dense(int dim, int mi, int mt, const double *Ainv, const T *r, T *z, double *w, hipStream_t s);
+template <typename S>
+int launch_convert(const double *in, S *out, long n, hipStream_t s);
+
 // Bytes of the per-workgroup arena of each kernel family (0 if not compiled in).
 size_t patch_arena_bytes(int dim, int prec, int p, int hcode);
 size_t apply_arena_bytes(int dim, int prec, int p);
+size_t metric_patch_arena_bytes(int dim, int prec, int p);
+size_t metric_apply_arena_bytes(int dim, int prec, int p);
 
 template <typename T>
 int launch_smooth_color(int dim, int p, int hcode, const SmoothArgs<T> &a, const Arena &ar, hipStream_t s);

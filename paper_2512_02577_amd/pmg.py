@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpmg.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_BF16 = 0, 1, 2
 LOCAL_HALF_V, LOCAL_FULL_V = 0, 1
 
 
@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
                                         P(ctypes.c_int64), P(ctypes.c_int32), P(_dp)]),
             "pmg_export_maps": (_ip, [_vp, _ip, _ip, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32),
                                       P(ctypes.c_uint8)]),
+            "pmg_get_qpoints": (_ip, [_vp, _ip, _ip, P(_dp)]),
+            "pmg_set_coefficient": (_ip, [_vp, _ip, _ip, P(_dp)]),
             "pmg_device_init": (_ip, [_vp]),
             "pmg_apply_operator": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp]),
             "pmg_residual": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp, _vp]),
@@ -105,13 +107,13 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _prec_of(t) -> int:
+def _prec_of(t, bf16: bool = False) -> int:
     import torch
 
     if t.dtype == torch.float64:
         return FP64
     if t.dtype == torch.float32:
-        return FP32
+        return FP32_BF16 if bf16 else FP32
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
@@ -212,13 +214,42 @@ def export_maps(pr: Problem, hlevel: int, plevel: int) -> dict[str, np.ndarray]:
     return {"cell_dofs": cd, "patch_interior": pi, "patch_closure": pc, "patch_color": col}
 
 
+def get_qpoints(pr: Problem, hlevel: int, plevel: int) -> np.ndarray:
+    """Physical Gauss points, shape (cells, (q+1)^dim, dim)."""
+    q = pr.degrees[plevel]
+    out = np.empty((pr.cells[hlevel] ** pr.dim, (q + 1) ** pr.dim, pr.dim), dtype=np.float64)
+    _check(lib().pmg_get_qpoints(pr.handle, hlevel, plevel, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def set_coefficient(pr: Problem, hlevel: int, plevel: int, a_q: np.ndarray | None) -> None:
+    ptr = None
+    if a_q is not None:
+        a_q = np.ascontiguousarray(a_q, dtype=np.float64)
+        q = pr.degrees[plevel]
+        if a_q.size != pr.cells[hlevel] ** pr.dim * (q + 1) ** pr.dim:
+            raise ValueError("one coefficient value per Gauss point expected")
+        ptr = a_q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().pmg_set_coefficient(pr.handle, hlevel, plevel, ptr))
+
+
+def set_coefficient_field(pr: Problem, field) -> None:
+    """Evaluates field(x) (x: (npoints, dim) array) at the Gauss points of every h- and
+    p-level and passes the values to the library."""
+    for hl in range(pr.n_hlevels):
+        for pl in range(pr.n_plevels):
+            x = get_qpoints(pr, hl, pl)
+            set_coefficient(pr, hl, pl, field(x.reshape(-1, pr.dim)))
+
+
 def device_init(pr: Problem) -> None:
     _check(lib().pmg_device_init(pr.handle))
 
 
-def apply_operator(pr: Problem, hlevel: int, u, v) -> None:
+def apply_operator(pr: Problem, hlevel: int, u, v, bf16: bool = False) -> None:
     n = _nodes(pr, hlevel)
-    _check(lib().pmg_apply_operator(pr.handle, hlevel, _prec_of(u), _ptr(u, n), _ptr(v, n, u.dtype), _stream()))
+    _check(lib().pmg_apply_operator(pr.handle, hlevel, _prec_of(u, bf16), _ptr(u, n), _ptr(v, n, u.dtype),
+                                    _stream()))
 
 
 def residual(pr: Problem, hlevel: int, b, u, r) -> None:
@@ -227,9 +258,10 @@ def residual(pr: Problem, hlevel: int, b, u, r) -> None:
                               _stream()))
 
 
-def smooth(pr: Problem, hlevel: int, u, b, color_dir: int = 1) -> None:
+def smooth(pr: Problem, hlevel: int, u, b, color_dir: int = 1, bf16: bool = False) -> None:
     n = _nodes(pr, hlevel)
-    _check(lib().pmg_smooth(pr.handle, hlevel, _prec_of(u), color_dir, _ptr(u, n), _ptr(b, n, u.dtype), _stream()))
+    _check(lib().pmg_smooth(pr.handle, hlevel, _prec_of(u, bf16), color_dir, _ptr(u, n), _ptr(b, n, u.dtype),
+                            _stream()))
 
 
 def local_solve(pr: Problem, hlevel: int, r, d, first_patch: int = 0) -> None:
@@ -277,11 +309,13 @@ def solve(pr: Problem, b, x, mg_prec: int = FP64, x_is_initial_guess: bool = Fal
 
 
 def make_problem(dim: int, n: int, p: int, p_levels=None, n_hlevels: int = 0, config: Config | None = None,
-                 device: bool = True) -> Problem:
-    """setup_mesh + setup_dofmap (+ device_init)."""
-    mesh = setup_mesh(dim, n, n_hlevels)
+                 device: bool = True, vertices: np.ndarray | None = None, coefficient=None) -> Problem:
+    """setup_mesh + setup_dofmap (+ coefficient at every level's Gauss points) (+ device_init)."""
+    mesh = setup_mesh(dim, n, n_hlevels, vertices)
     pr = setup_dofmap(mesh, p, p_levels, config)
     pr._mesh = mesh
+    if coefficient is not None:
+        set_coefficient_field(pr, coefficient)
     if device:
         device_init(pr)
     return pr

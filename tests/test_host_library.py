@@ -90,9 +90,12 @@ def test_levels_and_errors():
     with pytest.raises(pmg.PmgError) as e:
         pmg.setup_dofmap(pmg.setup_mesh(3, 8), 5, [1, 2, 5])  # valid list, not compiled in
     assert e.value.status == pmg.ERR_UNSUPPORTED
+    verts = np.zeros((729, 3))
+    pmg.setup_mesh(3, 8, 0, verts)  # distorted meshes are accepted (general path)
+    verts[5, 1] = np.nan
     with pytest.raises(pmg.PmgError) as e:
-        pmg.setup_mesh(3, 8, 0, np.zeros((729, 3)))
-    assert e.value.status == pmg.ERR_UNSUPPORTED
+        pmg.setup_mesh(3, 8, 0, verts)
+    assert e.value.status == pmg.ERR_INVALID_ARG
     cfg = pmg.default_config()
     cfg.rtol = 0.0
     with pytest.raises(pmg.PmgError):

@@ -114,3 +114,67 @@ def test_coarse_solve(emu, dim, n0, p):
     assert emu.pmgemu_coarse_solve(dim, n0, p, P(r), P(z)) == 0
     ref = pb.coarse_solve(r)
     assert abs(z - ref).max() <= 1e-12 * abs(ref).max()
+
+
+# ---- general path: distorted cells and a variable coefficient -------------------------
+from oracle.assembly import quadrature_points  # noqa: E402
+from paper_2512_02577_amd.inputs import CoefficientField, jittered_vertices  # noqa: E402
+
+GENERAL = [(2, 3, 2, 0.15, True), (2, 4, 4, 0.2, True), (2, 3, 7, 0.1, False), (3, 2, 2, 0.1, False),
+           (3, 3, 3, 0.1, True), (3, 2, 4, 0.1, True), (3, 2, 6, 0.1, True)]
+
+
+def _general_setup(dim, n, p, jit, use_coef):
+    verts = jittered_vertices(dim, n, jit, 3) if jit else None
+    field = CoefficientField(dim, 5) if use_coef else None
+    mesh = StructuredMesh(dim, n, verts)
+    V = np.ascontiguousarray(verts) if verts is not None else None
+    return mesh, field, V
+
+
+def _coef(mesh, field, q):
+    if field is None:
+        return None
+    return np.ascontiguousarray(field(quadrature_points(mesh, q).reshape(-1, mesh.dim)))
+
+
+@pytest.mark.parametrize("dim,n,p,jit,use_coef", GENERAL)
+def test_general_apply(emu, dim, n, p, jit, use_coef):
+    mesh, field, V = _general_setup(dim, n, p, jit, use_coef)
+    A = stiffness_matrix(mesh, p, field)
+    u = np.random.default_rng(1).uniform(-1, 1, A.shape[0])
+    b = rhs_vector(dim, n, p, 2)
+    c = _coef(mesh, field, p)
+    for resid in (0, 1):
+        out = np.zeros_like(u)
+        assert emu.pmgemu_metric_apply(dim, n, p, P(V) if V is not None else None, P(c) if c is not None else None,
+                                       resid, P(u), P(b), P(out)) == 0
+        ref = b - A @ u if resid else A @ u
+        assert abs(out - ref).max() <= 1e-13 * abs(ref).max()
+
+
+@pytest.mark.parametrize("dim,n,p,jit,use_coef", GENERAL)
+def test_general_smoother_and_local_solve(emu, dim, n, p, jit, use_coef):
+    mesh, field, V = _general_setup(dim, n, p, jit, use_coef)
+    deg = p_hierarchy(p)
+    om = [1.0] + [0.62] * (len(deg) - 1)
+    coefs = [_coef(mesh, field, q) for q in deg]
+    carr = (DP * len(deg))(*[P(x) if x is not None else None for x in coefs])
+    b = rhs_vector(dim, n, p, 3)
+    u0 = np.random.default_rng(4).uniform(-1, 1, len(b))
+    for local, it, direction in (("half", 1, 1), ("full", 2, -1)):
+        ls = LevelSmoother(mesh, deg, omega=om, coef=field, local=local, n_local_iter=it)
+        u = u0.copy()
+        assert emu.pmgemu_metric_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), it, direction,
+                                        P(V) if V is not None else None, carr, P(u), P(b), 0, None, None) == 0
+        ref = ls.smooth(u0, b, descending=direction < 0)
+        assert abs(u - ref).max() <= 1e-12 * abs(ref).max()
+    ls = LevelSmoother(mesh, deg, omega=om, coef=field, local="half")
+    nb, nd = ls.interior[-1].shape
+    r = np.random.default_rng(0).uniform(-1, 1, nb * nd)
+    d = np.zeros_like(r)
+    assert emu.pmgemu_metric_smooth(dim, n, p, ci(deg), len(deg), cd(om), 0, 1, 1, P(V) if V is not None else None,
+                                    carr, None, None, nb, P(r), P(d)) == 0
+    for j in range(nb):
+        ref = ls.local_solve(j, r[j * nd:(j + 1) * nd])
+        assert abs(d[j * nd:(j + 1) * nd] - ref).max() <= 1e-12 * abs(ref).max()
