@@ -66,6 +66,61 @@ def cpu_baseline(dim, n, p, seed, budget_s=12.0):
     return pb.N * k / t, k, t
 
 
+# 16 independent 3D Cartesian problems (n cells per direction, degree p), seeds 500 + k
+BATCH = [(16, 2), (24, 3), (32, 4), (48, 5), (16, 6), (24, 7), (32, 2), (48, 3), (16, 4), (24, 5), (32, 6), (48, 7),
+         (16, 7), (24, 6), (32, 5), (48, 4)]
+
+
+def bench_batch(steps, torch, pmg, rhs_vector):
+    """The 16-problem batch: FP32 multigrid in FP64 flexible CG, all problems in one batch
+    (persistent stage launches, graph-captured), against the same 16 solves one by one."""
+    dev = "cuda:0"
+    probs = [pmg.make_problem(3, n, p) for n, p in BATCH]
+    Ns = [pr.n_nodes[-1] for pr in probs]
+    bs = [torch.as_tensor(rhs_vector(3, n, p, 500 + k), dtype=torch.float64, device=dev)
+          for k, (n, p) in enumerate(BATCH)]
+    xs = [torch.empty_like(b) for b in bs]
+    cache = os.path.join(ROOT, "paper_2512_02577_amd", "tuning", "launch_params.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    t0 = time.perf_counter()
+    bt = pmg.batch_create(probs, cache)
+    t_create = time.perf_counter() - t0
+    pmg.batch_solve(bt, bs, xs, pmg.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = pmg.batch_solve(bt, bs, xs, pmg.FP32)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    its = [i.iterations for i in infos]
+    worst = max(i.rel_residual for i in infos)
+    # one batched V-cycle (graph launch; includes copying r in and z out)
+    zs = [torch.empty_like(b) for b in bs]
+    t_vc = time_events(lambda: pmg.batch_vcycle(bt, bs, zs, pmg.FP32), 5, torch)
+    stages, launches = pmg.batch_stats(bt, pmg.FP32)
+    # the same solves one problem at a time
+    for pr, b, x in zip(probs, bs, xs):
+        pmg.solve(pr, b, x, pmg.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its1 = []
+    for _ in range(steps):
+        its1 = [pmg.solve(pr, b, x, pmg.FP32).iterations for pr, b, x in zip(probs, bs, xs)]
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / steps
+    work = sum(N * k for N, k in zip(Ns, its))
+    return {"workload": "16 independent 3D Poisson problems, Cartesian, meshes 16^3..48^3, Q2..Q7, "
+                        "FP32 h-MG(V(1,1), vertex-patch smoother, local half V-cycle) in FP64 flexible CG to 1e-8",
+            "problems": [f"{n}^3 Q{p}" for n, p in BATCH], "n_dofs": sum(Ns),
+            "value": work / t_batch, "unit": "DoF/s per V-cycle",
+            "time_to_solution_s": t_batch, "iterations": its, "max_rel_residual": worst,
+            "vcycle_ms": t_vc, "vcycle_dof_per_s": sum(Ns) / (t_vc * 1e-3),
+            "stages_per_vcycle": stages, "launches_per_vcycle": launches,
+            "one_by_one_time_s": t_seq, "one_by_one_iterations": its1,
+            "one_by_one_dof_per_s_per_vcycle": sum(N * k for N, k in zip(Ns, its1)) / t_seq,
+            "speedup_vs_one_by_one": t_seq / t_batch, "create_and_tune_s": t_create}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +128,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-batch", action="store_true", help="leave out the 16-problem batch measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -188,6 +244,9 @@ def main():
         "smooth_over_apply": t_smooth / t_apply,
         "roofline": roof,
     }
+    if not args.no_batch:
+        log("bench: 16-problem batch (FP32-MG in FP64 CG) and the same solves one by one")
+        out["batched"] = bench_batch(max(1, min(args.steps, 3)), torch, pmg, rhs_vector)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline (8^3 cells, Q4, V-cycles, one thread)")
         rate, k, t = cpu_baseline(3, 8, 4, seed)

@@ -25,7 +25,8 @@
  *   - Dirichlet rows are identity rows: (A u)_i = u_i on boundary nodes and interior rows
  *     do not see boundary values.
  *   - Streams are hipStream_t passed as void*; NULL is the default stream.  Device entry
- *     points enqueue work and return without synchronizing, except pmg_solve.
+ *     points enqueue work and return without synchronizing, except pmg_solve and
+ *     pmg_batch_solve.
  *   - Every function returns PMG_OK (0) or a negative status; pmg_last_error() gives a
  *     thread-local message.  Arguments are validated before anything is enqueued, so a
  *     failed call leaves its outputs untouched.  No C++ exception crosses the interface.
@@ -208,6 +209,56 @@ int pmg_solve(pmg_problem *pr, int mg_prec, const double *b, double *x, int x_is
               pmg_solve_info *info, void *stream);
 
 void pmg_destroy_problem(pmg_problem *pr);
+
+/* ---- Batches of independent problems (an extension: the paper solves one problem at
+ * a time and names the barriers between colors as the main cost on coarse meshes,
+ * Sec. 4.4) ----
+ *
+ * A batch holds up to PMG_BATCH_MAX device-initialized problems of the Cartesian 3D path
+ * with the paper's p-hierarchy (Sec. 2.2), any mix of mesh sizes and degrees.  Their
+ * V-cycles are aligned by depth below the finest level: each V-cycle stage (one color
+ * sweep, the residual, one 1D transfer pass, the coarse solves, ...) of all problems is
+ * one persistent launch per register class of degrees (p <= 4, p = 5..6, p = 7..8), and
+ * the whole cycle, together with the vector updates of the outer flexible CG, is captured
+ * once as a HIP graph.  The arithmetic of every problem equals that of pmg_vcycle and
+ * pmg_solve on it (the same kernel bodies and tables); only the reduction trees of the
+ * CG dot products differ.
+ *
+ * The batch uses the problems' own work buffers: while a batch call runs, no other call
+ * may use its problems, and a problem may belong to several batches used one at a time.
+ * The problems must outlive the batch.  Batch entry points are not thread-safe for one
+ * batch. */
+#define PMG_BATCH_MAX 16
+typedef struct pmg_batch pmg_batch;
+
+/* Builds the stage tables of both multigrid precisions (PMG_FP64 only where every
+ * degree's patch arena fits in LDS, i.e. p <= 7), allocates the batch state and chooses
+ * the launch parameters: the persistent grid per kernel class and the apply tile per
+ * degree.  tuning_cache_path: NULL uses built-in defaults; otherwise a JSON object of
+ * "arch/precision/knob": value entries is read, missing entries are measured on the
+ * device (a few seconds, the problems' work buffers are overwritten) and the file is
+ * rewritten with them.  Errors: INVALID_ARG (n outside [1, PMG_BATCH_MAX], NULL or
+ * repeated problems, a problem without pmg_device_init or on another device),
+ * UNSUPPORTED (2D, general path, or a p-hierarchy other than the paper's). */
+int pmg_batch_create(pmg_problem *const *problems, int n, const char *tuning_cache_path, pmg_batch **out);
+
+/* Launches and stages of one V-cycle of the batch in mg_prec (for inspection). */
+int pmg_batch_stats(const pmg_batch *bt, int mg_prec, int *n_stages, int *n_launches);
+
+/* z[k] = V_k(r[k]) for every problem k of the batch, as pmg_vcycle (float64 vectors on
+ * the finest level of problem k; mg_prec as there).  Enqueues without synchronizing. */
+int pmg_batch_vcycle(pmg_batch *bt, int mg_prec, const double *const *r, double *const *z, void *stream);
+
+/* Solves A_k x[k] = b[k] for every problem k by the flexible CG of pmg_solve from a zero
+ * guess, all problems iterating together; a problem stops iterating once it meets its
+ * own rtol (or breaks down, or reaches its max_iter) while the others go on.
+ * infos[k] (may be NULL) receives its iterations, relative residual, status, and the
+ * wall time of the whole batch solve.  Synchronizes once per iteration.  Returns PMG_OK
+ * when every problem converged, else the status of the first problem that did not. */
+int pmg_batch_solve(pmg_batch *bt, int mg_prec, const double *const *b, double *const *x, pmg_solve_info *infos,
+                    void *stream);
+
+void pmg_destroy_batch(pmg_batch *bt);
 
 #ifdef __cplusplus
 }

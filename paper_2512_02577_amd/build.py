@@ -25,7 +25,8 @@ EMU = os.path.join(PKG, "libpmg_hostemu.so")
 HIP_SOURCES = ["kernels_metric_3d_f32.hip", "kernels_metric_3d_bf16.hip", "kernels_metric_3d_f64.hip",
                "kernels_metric_2d_f64.hip", "kernels_metric_2d_f32.hip",
                "kernels_3d_f64.hip", "kernels_3d_f32.hip", "kernels_2d_f64.hip", "kernels_2d_f32.hip",
-               "setup.hip", "blas.hip", "capi.cpp", "kernels_dispatch.cpp", "host_tables.cpp", "geometry.cpp"]
+               "setup.hip", "blas.hip", "batch.hip", "capi.cpp", "batch_host.cpp", "kernels_dispatch.cpp",
+               "host_tables.cpp", "geometry.cpp"]
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
                # no packed FP32 instructions anywhere in the device code
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -52,7 +53,7 @@ def build_hip(jobs: int = 8) -> str:
     cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src in ("capi.cpp", "kernels_dispatch.cpp") else []
+        lang = ["-x", "hip"] if src in ("capi.cpp", "batch_host.cpp", "kernels_dispatch.cpp") else []
         cmds.append([hipcc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(cmds)))) as ex:

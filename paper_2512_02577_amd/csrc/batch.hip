@@ -1,0 +1,376 @@
+// Batched stage kernels: persistent grids that walk the concatenated work items of all
+// problems of one V-cycle stage, and the FP64 vector kernels of the batched outer CG.
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "dispatch.h"
+#include "launch.h"
+
+namespace pmg {
+
+namespace {
+
+template <typename T>
+__device__ inline T *lds_arena() {
+  extern __shared__ __align__(16) unsigned char smem[];
+  return reinterpret_cast<T *>(smem);
+}
+
+// Segment of work item `item` (segments sorted by start, at most kBatchMax of them).
+template <typename Stage>
+__device__ inline int seg_of(const cptr<Stage> &st, int nseg, long item) {
+  int s = 0;
+  while (s + 1 < nseg && st->seg[s + 1].start <= item) ++s;
+  return s;
+}
+
+// PLO..PHI: the degrees compiled into this kernel (one register class).
+template <typename T, int PLO, int PHI>
+__global__ __launch_bounds__(kBatchThreads) void k_bsmooth(const BSmoothStage<T> *st_) {
+  const cptr<BSmoothStage<T>> st = as_const(st_);
+  T *lds = lds_arena<T>();
+  const int nseg = st->nseg, total = st->total;
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int s = seg_of(st, nseg, blk);
+    if (!as_const(st->active)[st->seg[s].prob]) continue;
+    SmoothArgs<T> a;
+    a = st->seg[s].a;
+    const int local = blk - st->seg[s].start;
+    switch (st->seg[s].p) {
+#define PMG_BS(P)                                                                                            \
+  case P:                                                                                                    \
+    if constexpr (P >= PLO && P <= PHI)                                                                      \
+      PatchBody<3, T, kBatchThreads, P, typename PaperH<P>::type>::smooth_patch(threadIdx.x, local, lds, a); \
+    break;
+      PMG_BS(1) PMG_BS(2) PMG_BS(3) PMG_BS(4) PMG_BS(5) PMG_BS(6) PMG_BS(7) PMG_BS(8)
+#undef PMG_BS
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int P, int OPT, bool RESID>
+__device__ inline void apply_tile(int local, T *lds, const ApplyArgs<T> &a) {
+  if constexpr (OPT == 0 || batch_tile(P, 1) != batch_tile(P, 0))
+    ApplyBody<3, T, kBatchThreads, P, batch_tile(P, OPT), RESID>::run(threadIdx.x, local, lds, a);
+}
+
+template <typename T, int PLO, int PHI, bool RESID>
+__global__ __launch_bounds__(kBatchThreads) void k_bapply(const BApplyStage<T> *st_) {
+  const cptr<BApplyStage<T>> st = as_const(st_);
+  T *lds = lds_arena<T>();
+  const int nseg = st->nseg, total = st->total;
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int s = seg_of(st, nseg, blk);
+    if (!as_const(st->active)[st->seg[s].prob]) continue;
+    ApplyArgs<T> a;
+    a = st->seg[s].a;
+    const int local = blk - st->seg[s].start;
+    switch (st->seg[s].p * 2 + st->seg[s].tile) {
+#define PMG_BA(P)                                                     \
+  case 2 * P:                                                         \
+    if constexpr (P >= PLO && P <= PHI) apply_tile<T, P, 0, RESID>(local, lds, a); \
+    break;                                                            \
+  case 2 * P + 1:                                                     \
+    if constexpr (P >= PLO && P <= PHI) apply_tile<T, P, 1, RESID>(local, lds, a); \
+    break;
+      PMG_BA(1) PMG_BA(2) PMG_BA(3) PMG_BA(4) PMG_BA(5) PMG_BA(6) PMG_BA(7) PMG_BA(8)
+#undef PMG_BA
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int P>
+__device__ inline void pass_item(int mode, long g, const PassArgs<T> &pa) {
+  if (mode == 0)
+    TransferPass<T, P, true, false>::node(g, pa);
+  else if (mode == 1)
+    TransferPass<T, P, false, false>::node(g, pa);
+  else
+    TransferPass<T, P, false, true>::node(g, pa);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBatchThreads) void k_bpass(const BPassStage<T> *st_) {
+  const cptr<BPassStage<T>> st = as_const(st_);
+  const int nseg = st->nseg;
+  const long tt = st->total_threads;
+  for (long g0 = (long)blockIdx.x * kBatchThreads; g0 < tt; g0 += (long)gridDim.x * kBatchThreads) {
+    // segments start at multiples of the workgroup size: the segment is uniform per block
+    const int s = seg_of(st, nseg, g0);
+    const long local = g0 - st->seg[s].start + threadIdx.x;
+    if (local >= st->seg[s].total || !as_const(st->active)[st->seg[s].prob]) continue;
+    PassArgs<T> pa;
+    pa = st->seg[s].pa;
+    const int mode = st->seg[s].mode;
+    switch (st->seg[s].p) {
+      case 1: pass_item<T, 1>(mode, local, pa); break;
+      case 2: pass_item<T, 2>(mode, local, pa); break;
+      case 3: pass_item<T, 3>(mode, local, pa); break;
+      case 4: pass_item<T, 4>(mode, local, pa); break;
+      case 5: pass_item<T, 5>(mode, local, pa); break;
+      case 6: pass_item<T, 6>(mode, local, pa); break;
+      case 7: pass_item<T, 7>(mode, local, pa); break;
+      case 8: pass_item<T, 8>(mode, local, pa); break;
+      default: break;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bcoarse(const BCoarseStage<T> *st_) {
+  const cptr<BCoarseStage<T>> st = as_const(st_);
+  if (!as_const(st->active)[st->prob[blockIdx.x]]) return;
+  CoarseArgs<T> a;
+  a = st->seg[blockIdx.x];
+  CoarseBody<3, T, 256>::run(threadIdx.x, a);
+}
+
+// kind 0: z = 0 on interior nodes, z = r on boundary nodes (in = r, out = z, type T)
+// kind 1: out (T) = in (double)            kind 2: out (double) = in (T)
+// kind 3: out (double) = in (double)
+template <typename T>
+__global__ __launch_bounds__(256) void k_belem(const BElemStage *st_) {
+  const cptr<BElemStage> st = as_const(st_);
+  const int nseg = st->nseg, kind = st->kind;
+  const long tot = st->total;
+  for (long g0 = (long)blockIdx.x * 256; g0 < tot; g0 += (long)gridDim.x * 256) {
+    const int s = seg_of(st, nseg, g0);
+    const long i = g0 - st->seg[s].start + threadIdx.x;
+    if (i >= st->seg[s].count || !as_const(st->active)[st->seg[s].prob]) continue;
+    if (kind == 0) {
+      const int m = st->seg[s].m;
+      const int x = (int)(i % m), y = (int)((i / m) % m), z = (int)(i / ((long)m * m));
+      const bool bnd = x == 0 || x == m - 1 || y == 0 || y == m - 1 || z == 0 || z == m - 1;
+      ((T *)st->seg[s].out)[i] = bnd ? ((const T *)st->seg[s].in)[i] : T(0);
+    } else if (kind == 1) {
+      ((T *)st->seg[s].out)[i] = (T)((const double *)st->seg[s].in)[i];
+    } else if (kind == 2) {
+      ((double *)st->seg[s].out)[i] = (double)((const T *)st->seg[s].in)[i];
+    } else {
+      ((double *)st->seg[s].out)[i] = ((const double *)st->seg[s].in)[i];
+    }
+  }
+}
+
+template <typename T>
+struct SmoothBytes {
+  template <int P>
+  struct F {
+    static int run(size_t *o) {
+      *o = PatchBody<3, T, kBatchThreads, P, typename PaperH<P>::type>::size * sizeof(T);
+      return 0;
+    }
+  };
+};
+
+template <typename T>
+struct ApplyBytes {
+  template <int P>
+  struct F {
+    static int run(int opt, size_t *o) {
+      *o = (opt == 0 ? ApplyBody<3, T, kBatchThreads, P, batch_tile(P, 0), false>::size
+                     : ApplyBody<3, T, kBatchThreads, P, batch_tile(P, 1), false>::size) *
+           sizeof(T);
+      return 0;
+    }
+  };
+};
+
+int ok() { return hipGetLastError() == hipSuccess ? 0 : -4; }
+
+// ---- batched FCG vectors ----
+constexpr int kT = 256;
+
+__device__ inline double block_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = kT / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// grid = blocks; block b handles chunk b - start of the segment that holds it
+__global__ __launch_bounds__(kT) void k_bvec(const BVecStage *st_, int op) {
+  __shared__ double sh[kT];
+  const cptr<BVecStage> st = as_const(st_);
+  const int seg = seg_of(st, st->nseg, blockIdx.x);
+  const int bps = st->seg[seg].bps, chunk = blockIdx.x - st->seg[seg].start;
+  const long n = st->seg[seg].n;
+  const bool act = as_const(st->active)[seg] != 0;
+  const double *scal = st->scal + seg * S_COUNT;
+  double *part = st->part + 2L * st->seg[seg].start;
+  double *x = st->seg[seg].x, *r = st->seg[seg].r, *ro = st->seg[seg].rold, *z = st->seg[seg].z;
+  double *p = st->seg[seg].p, *q = st->seg[seg].q;
+  if (!act) return;  // uniform per block
+  const long stride = (long)bps * kT, i0 = (long)chunk * kT + threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  if (op == 0) {
+    for (long i = i0; i < n; i += stride) s0 += p[i] * q[i];
+  } else if (op == 1) {
+    const double alpha = scal[S_ALPHA];
+    for (long i = i0; i < n; i += stride) {
+      const double ri = r[i];
+      x[i] += alpha * p[i];
+      ro[i] = ri;
+      const double rn = ri - alpha * q[i];
+      r[i] = rn;
+      s0 += rn * rn;
+    }
+  } else if (op == 2) {
+    for (long i = i0; i < n; i += stride) {
+      s0 += z[i] * r[i];
+      s1 += z[i] * ro[i];
+    }
+  } else if (op == 3) {
+    const double beta = scal[S_BETA];
+    for (long i = i0; i < n; i += stride) p[i] = z[i] + beta * p[i];
+    return;
+  } else {
+    for (long i = i0; i < n; i += stride) s0 += r[i] * r[i];
+  }
+  s0 = block_sum(s0, sh);
+  s1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) {
+    part[chunk] = s0;
+    part[bps + chunk] = s1;
+  }
+}
+
+// one block per segment: sum the partials in a fixed order and update the scalars
+__global__ __launch_bounds__(kT) void k_bvec_final(const BVecStage *st_, int op) {
+  __shared__ double sh[kT];
+  const cptr<BVecStage> st = as_const(st_);
+  const int seg = blockIdx.x, bps = st->seg[seg].bps;
+  const bool act = as_const(st->active)[seg] != 0;
+  double *scal = st->scal + seg * S_COUNT;
+  const double *part = st->part + 2L * st->seg[seg].start;
+  if (!act) return;  // uniform per block
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < bps; i += kT) {
+    a += part[i];
+    b += part[bps + i];
+  }
+  a = block_sum(a, sh);
+  b = block_sum(b, sh);
+  if (threadIdx.x != 0) return;
+  if (op == 0) {
+    scal[S_PQ] = a;
+    scal[S_ALPHA] = scal[S_RZ] / a;
+  } else if (op == 1) {
+    scal[S_RR] = a;
+  } else if (op == 2) {
+    scal[S_ZRN] = a;
+    scal[S_ZRO] = b;
+    scal[S_BETA] = (a - b) / scal[S_RZ];
+    scal[S_RZ] = a;
+  } else if (op == 4) {
+    scal[S_BB] = a;
+    scal[S_RR] = a;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+size_t BatchLaunch<T>::smooth_bytes(int p) {
+  size_t o = 0;
+  return dispatch_degree<SmoothBytes<T>::template F>(p, &o) == 0 ? o : 0;
+}
+
+template <typename T>
+size_t BatchLaunch<T>::apply_bytes(int p, int tile) {
+  size_t o = 0;
+  return dispatch_degree<ApplyBytes<T>::template F>(p, tile, &o) == 0 ? o : 0;
+}
+
+template <typename T>
+int BatchLaunch<T>::prepare(size_t shmem) {
+  if (shmem <= 65536) return 0;
+  const void *ks[] = {(const void *)k_bsmooth<T, 1, 4>,        (const void *)k_bsmooth<T, 5, 6>,
+                      (const void *)k_bsmooth<T, 7, 8>,        (const void *)k_bapply<T, 1, 4, true>,
+                      (const void *)k_bapply<T, 5, 6, true>,   (const void *)k_bapply<T, 7, 8, true>,
+                      (const void *)k_bapply<T, 1, 4, false>,  (const void *)k_bapply<T, 5, 6, false>,
+                      (const void *)k_bapply<T, 7, 8, false>};
+  for (const void *k : ks)
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess) return -4;
+  return 0;
+}
+
+
+template <typename T>
+int BatchLaunch<T>::smooth(const BSmoothStage<T> *st, int cls, int grid, size_t shmem, hipStream_t s) {
+  if (grid <= 0) return 0;
+  if (cls == 0)
+    hipLaunchKernelGGL((k_bsmooth<T, 1, 4>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+  else if (cls == 1)
+    hipLaunchKernelGGL((k_bsmooth<T, 5, 6>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+  else
+    hipLaunchKernelGGL((k_bsmooth<T, 7, 8>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+  return ok();
+}
+
+template <typename T>
+int BatchLaunch<T>::apply(const BApplyStage<T> *st, int cls, bool resid, int grid, size_t shmem, hipStream_t s) {
+  if (grid <= 0) return 0;
+  if (resid) {
+    if (cls == 0)
+      hipLaunchKernelGGL((k_bapply<T, 1, 4, true>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+    else if (cls == 1)
+      hipLaunchKernelGGL((k_bapply<T, 5, 6, true>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+    else
+      hipLaunchKernelGGL((k_bapply<T, 7, 8, true>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+  } else {
+    if (cls == 0)
+      hipLaunchKernelGGL((k_bapply<T, 1, 4, false>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+    else if (cls == 1)
+      hipLaunchKernelGGL((k_bapply<T, 5, 6, false>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+    else
+      hipLaunchKernelGGL((k_bapply<T, 7, 8, false>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
+  }
+  return ok();
+}
+
+template <typename T>
+int BatchLaunch<T>::pass(const BPassStage<T> *st, int grid, hipStream_t s) {
+  if (grid <= 0) return 0;
+  hipLaunchKernelGGL(k_bpass<T>, dim3(grid), dim3(kBatchThreads), 0, s, st);
+  return ok();
+}
+
+template <typename T>
+int BatchLaunch<T>::coarse(const BCoarseStage<T> *st, int nseg, hipStream_t s) {
+  if (nseg <= 0) return 0;
+  hipLaunchKernelGGL(k_bcoarse<T>, dim3(nseg), dim3(256), 0, s, st);
+  return ok();
+}
+
+template <typename T>
+int BatchLaunch<T>::elem(const BElemStage *st, int grid, hipStream_t s) {
+  if (grid <= 0) return 0;
+  hipLaunchKernelGGL(k_belem<T>, dim3(grid), dim3(256), 0, s, st);
+  return ok();
+}
+
+template struct BatchLaunch<double>;
+template struct BatchLaunch<float>;
+
+int launch_bvec(const BVecStage *st, int op, int nseg, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_bvec, dim3(blocks), dim3(kT), 0, s, st, op);
+  if (hipGetLastError() != hipSuccess) return -4;
+  if (op == 3) return 0;
+  hipLaunchKernelGGL(k_bvec_final, dim3(nseg), dim3(kT), 0, s, st, op);
+  return ok();
+}
+
+}  // namespace pmg

@@ -19,6 +19,7 @@
 #include "host_tables.h"
 #include "launch.h"
 #include "pmg.h"
+#include "problem.h"
 
 using namespace pmg;
 
@@ -26,7 +27,9 @@ namespace {
 
 thread_local std::string g_err;
 
-int fail(int code, const char *fmt, ...) {
+}  // namespace
+
+int pmg::fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -35,80 +38,6 @@ int fail(int code, const char *fmt, ...) {
   g_err = buf;
   return code;
 }
-
-#define PMG_TRY(expr)                                                        \
-  do {                                                                       \
-    int rc_ = (expr);                                                        \
-    if (rc_ != 0) return fail(rc_ == -3 ? PMG_ERR_OUT_OF_MEMORY : PMG_ERR_DEVICE, "%s failed (%d): %s", #expr, rc_, \
-                              hipGetErrorString(hipGetLastError()));         \
-  } while (0)
-
-#define PMG_HIP(expr)                                                                         \
-  do {                                                                                        \
-    hipError_t e_ = (expr);                                                                   \
-    if (e_ != hipSuccess)                                                                     \
-      return fail(e_ == hipErrorOutOfMemory ? PMG_ERR_OUT_OF_MEMORY : PMG_ERR_DEVICE, "%s: %s", #expr, \
-                  hipGetErrorString(e_));                                                     \
-  } while (0)
-
-template <typename T>
-struct PrecData {
-  DevTabs<T> tabs{};
-  std::vector<T *> r, z, t;   // per h-level work vectors
-  T *tw1 = nullptr, *tw2 = nullptr;  // intermediates of the 1D transfer passes
-};
-
-}  // namespace
-
-struct pmg_mesh {
-  int dim = 3, n = 0;
-  std::vector<int> sizes;   // cells per direction, coarsest first
-  std::vector<double> verts;  // finest-level vertices, empty for the Cartesian unit box
-};
-
-struct pmg_problem {
-  int dim = 3, p = 1, hcode = 0;
-  std::vector<int> sizes, degrees;
-  pmg_config cfg{};
-  Tables tab;
-  // device state
-  bool dev = false;
-  int device = -1;
-  std::vector<void *> allocs;
-  PrecData<double> d64;
-  PrecData<float> d32;
-  double *S0 = nullptr, *lam0 = nullptr, *cw1 = nullptr, *cw2 = nullptr;
-  double *fr[2] = {nullptr, nullptr}, *fz = nullptr, *fp = nullptr, *fq = nullptr;
-  double *part = nullptr, *scal = nullptr, *hscal = nullptr;
-  Arena arena;
-  // general path (distorted vertices or a coefficient): per (h-level, p-level) data
-  bool general = false;
-  std::vector<dvec> verts;                  // per h-level
-  std::vector<dvec> coef;                   // [hl * L + pl], empty = mu 1
-  std::vector<QTabDev<double>> qt64;        // per p-level
-  std::vector<QTabDev<float>> qt32;
-  std::vector<const double *> G64, invD64;  // [hl * L + pl]
-  std::vector<const float *> G32, invD32;
-  std::vector<const bf16 *> G16, invD16;
-  double *Ainv = nullptr, *cwork = nullptr; // dense coarse inverse and its gather vector
-  int coarse_mi = 0;
-
-  int nplev() const { return (int)degrees.size(); }
-  long cells(int l) const { return dim == 3 ? (long)sizes[l] * sizes[l] * sizes[l] : (long)sizes[l] * sizes[l]; }
-  long nodes(int l) const {
-    long m = (long)p * sizes[l] + 1;
-    return dim == 3 ? m * m * m : m * m;
-  }
-  int finest() const { return (int)sizes.size() - 1; }
-  double cscale(int l) const { return dim == 3 ? 1.0 / sizes[l] : 1.0; }
-  template <typename T>
-  PrecData<T> &pd();
-};
-
-template <>
-PrecData<double> &pmg_problem::pd<double>() { return d64; }
-template <>
-PrecData<float> &pmg_problem::pd<float>() { return d32; }
 
 namespace {
 

@@ -256,6 +256,16 @@ double patch_lambda_max(int dim, const PLevel &L) {
   return *std::max_element(ev.begin(), ev.end());
 }
 
+// apply tile of tc cells per direction: output nodes p*c0 .. p*(c0+tc)-1, input nodes
+// p*(c0-1) .. p*(c0+tc)
+void apply_tile_tables(int p, int tc, dvec &Kt, dvec &Mt) {
+  dvec K, M;
+  line_matrices(p, tc + 1, K, M);
+  const int NI = p * (tc + 1) + 1, NO = p * tc;
+  Kt = sub(K, NI, p, NO, 0, NI);
+  Mt = sub(M, NI, p, NO, 0, NI);
+}
+
 void build_tables(int dim, int p, const std::vector<int> &degrees, const dvec &omega_override,
                   int n_coarse, Tables &t) {
   t = Tables();
@@ -325,15 +335,8 @@ void build_tables(int dim, int p, const std::vector<int> &degrees, const dvec &o
     t.Kr = sub(K, Nc, 1, 2 * p - 1, 0, Nc);
     t.Mr = sub(M, Nc, 1, 2 * p - 1, 0, Nc);
   }
-  // apply tile: output nodes p*c0 .. p*(c0+tc)-1, input nodes p*(c0-1) .. p*(c0+tc)
-  {
-    t.tc = apply_tile_cells(p);
-    dvec K, M;
-    line_matrices(p, t.tc + 1, K, M);
-    int NI = p * (t.tc + 1) + 1, NO = p * t.tc;
-    t.Kt = sub(K, NI, p, NO, 0, NI);
-    t.Mt = sub(M, NI, p, NO, 0, NI);
-  }
+  t.tc = apply_tile_cells(p);
+  apply_tile_tables(p, t.tc, t.Kt, t.Mt);
   // h-embedding: coarse cell basis at the fine Gauss-Lobatto nodes of its two halves
   {
     dvec z = gauss_lobatto(p);

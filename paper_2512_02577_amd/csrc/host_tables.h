@@ -53,6 +53,9 @@ struct Tables {
 };
 
 int apply_tile_cells(int p);
+// 1D tables of an apply tile of tc cells per direction (rows: the tile's owned nodes,
+// columns: the tile plus one halo cell below).
+void apply_tile_tables(int p, int tc, dvec &Kt, dvec &Mt);
 
 // omega_override: empty for the default 4 / (3 lambda_max(D^{-1} A)) per level.
 void build_tables(int dim, int p, const std::vector<int> &degrees, const dvec &omega_override,

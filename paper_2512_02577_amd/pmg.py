@@ -76,6 +76,11 @@ def lib() -> ctypes.CDLL:
             "pmg_vcycle": (_ip, [_vp, _ip, _vp, _vp, _vp]),
             "pmg_solve": (_ip, [_vp, _ip, _vp, _vp, _ip, P(SolveInfo), _vp]),
             "pmg_destroy_problem": (None, [_vp]),
+            "pmg_batch_create": (_ip, [P(_vp), _ip, ctypes.c_char_p, P(_vp)]),
+            "pmg_batch_stats": (_ip, [_vp, _ip, P(_ip), P(_ip)]),
+            "pmg_batch_vcycle": (_ip, [_vp, _ip, P(_vp), P(_vp), _vp]),
+            "pmg_batch_solve": (_ip, [_vp, _ip, P(_vp), P(_vp), P(SolveInfo), _vp]),
+            "pmg_destroy_batch": (None, [_vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -319,3 +324,55 @@ def make_problem(dim: int, n: int, p: int, p_levels=None, n_hlevels: int = 0, co
     if device:
         device_init(pr)
     return pr
+
+
+BATCH_MAX = 16
+
+
+class Batch:
+    """Handle of a batch of problems (pmg_batch_create); keeps its problems alive."""
+
+    def __init__(self, handle: ctypes.c_void_p, problems: list[Problem]):
+        self.handle = handle
+        self.problems = problems
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.pmg_destroy_batch(self.handle)
+            self.handle = None
+
+
+def batch_create(problems: list[Problem], tuning_cache: str | None = None) -> Batch:
+    arr = (ctypes.c_void_p * len(problems))(*[pr.handle.value if isinstance(pr.handle, ctypes.c_void_p)
+                                              else pr.handle for pr in problems])
+    h = ctypes.c_void_p()
+    path = tuning_cache.encode() if tuning_cache else None
+    _check(lib().pmg_batch_create(arr, len(problems), path, ctypes.byref(h)))
+    return Batch(h, list(problems))
+
+
+def batch_stats(bt: Batch, mg_prec: int = FP32) -> tuple[int, int]:
+    st, la = ctypes.c_int(), ctypes.c_int()
+    _check(lib().pmg_batch_stats(bt.handle, mg_prec, ctypes.byref(st), ctypes.byref(la)))
+    return st.value, la.value
+
+
+def _vec_array(bt: Batch, ts) -> ctypes.Array:
+    import torch
+
+    if len(ts) != len(bt.problems):
+        raise ValueError(f"expected {len(bt.problems)} vectors, got {len(ts)}")
+    return (ctypes.c_void_p * len(ts))(*[_ptr(t, pr.n_nodes[pr.finest], torch.float64).value
+                                         for t, pr in zip(ts, bt.problems)])
+
+
+def batch_vcycle(bt: Batch, r, z, mg_prec: int = FP32) -> None:
+    _check(lib().pmg_batch_vcycle(bt.handle, mg_prec, _vec_array(bt, r), _vec_array(bt, z), _stream()))
+
+
+def batch_solve(bt: Batch, b, x, mg_prec: int = FP32, raise_on_failure: bool = True) -> list[SolveInfo]:
+    infos = (SolveInfo * len(bt.problems))()
+    rc = lib().pmg_batch_solve(bt.handle, mg_prec, _vec_array(bt, b), _vec_array(bt, x), infos, _stream())
+    if rc != OK and raise_on_failure:
+        raise PmgError(rc, last_error())
+    return list(infos)

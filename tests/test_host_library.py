@@ -112,3 +112,20 @@ def test_device_calls_before_init_fail_cleanly():
     info = pmg.SolveInfo()
     assert L.pmg_solve(pr.handle, 0, null, null, 0, ctypes.byref(info), null) == pmg.ERR_STATE
     assert "pmg_device_init" in pmg.last_error()
+
+
+def test_batch_rejects_problems_without_device_state():
+    L = pmg.lib()
+    pr = pmg.setup_dofmap(pmg.setup_mesh(3, 4), 2)
+    out = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 1)(pr.handle.value)
+    assert L.pmg_batch_create(arr, 1, None, ctypes.byref(out)) == pmg.ERR_INVALID_ARG
+    assert "pmg_device_init" in pmg.last_error()
+    assert L.pmg_batch_create(arr, 0, None, ctypes.byref(out)) == pmg.ERR_INVALID_ARG
+    arr17 = (ctypes.c_void_p * 17)(*([pr.handle.value] * 17))
+    assert L.pmg_batch_create(arr17, 17, None, ctypes.byref(out)) == pmg.ERR_INVALID_ARG
+    assert L.pmg_batch_create(None, 1, None, ctypes.byref(out)) == pmg.ERR_INVALID_ARG
+    assert L.pmg_batch_solve(None, pmg.FP32, None, None, None, None) == pmg.ERR_INVALID_ARG
+    assert L.pmg_batch_vcycle(None, pmg.FP32, None, None, None) == pmg.ERR_INVALID_ARG
+    assert L.pmg_batch_stats(None, pmg.FP32, None, None) == pmg.ERR_INVALID_ARG
+    L.pmg_destroy_batch(None)
