@@ -218,9 +218,9 @@ void pmg_destroy_problem(pmg_problem *pr);
  * with the paper's p-hierarchy (Sec. 2.2), any mix of mesh sizes and degrees.  Their
  * V-cycles are aligned by depth below the finest level: each V-cycle stage (one color
  * sweep, the residual, one 1D transfer pass, the coarse solves, ...) of all problems is
- * one persistent launch per register class of degrees (p <= 4, p = 5..6, p = 7..8), and
- * the whole cycle, together with the vector updates of the outer flexible CG, is captured
- * once as a HIP graph.  The arithmetic of every problem equals that of pmg_vcycle and
+ * one persistent launch per degree present (independent launches, run as parallel
+ * branches), and the whole cycle, together with the vector updates of the outer
+ * flexible CG, is captured once as a HIP graph.  The arithmetic of every problem equals that of pmg_vcycle and
  * pmg_solve on it (the same kernel bodies and tables); only the reduction trees of the
  * CG dot products differ.
  *
@@ -232,14 +232,16 @@ void pmg_destroy_problem(pmg_problem *pr);
 typedef struct pmg_batch pmg_batch;
 
 /* Builds the stage tables of both multigrid precisions (PMG_FP64 only where every
- * degree's patch arena fits in LDS, i.e. p <= 7), allocates the batch state and chooses
- * the launch parameters: the persistent grid per kernel class and the apply tile per
- * degree.  tuning_cache_path: NULL uses built-in defaults; otherwise a JSON object of
- * "arch/precision/knob": value entries is read, missing entries are measured on the
- * device (a few seconds, the problems' work buffers are overwritten) and the file is
- * rewritten with them.  Errors: INVALID_ARG (n outside [1, PMG_BATCH_MAX], NULL or
- * repeated problems, a problem without pmg_device_init or on another device),
- * UNSUPPORTED (2D, general path, or a p-hierarchy other than the paper's). */
+ * degree's patch arena fits in LDS, i.e. p <= 7) and allocates the batch state.  Launch
+ * parameters, per degree: persistent workgroups per CU of the patch and apply kernels,
+ * the apply tile; plus whether the launches of one stage run as parallel graph branches.
+ * tuning_cache_path: NULL uses built-in defaults; otherwise a JSON object of
+ * "arch/3d/precision/knob": value entries is read, and the first batch call in a
+ * precision measures the entries it lacks on the device (seconds: whole V-cycles per
+ * candidate, on the problems' work buffers) and rewrites the file with them.  Errors:
+ * INVALID_ARG (n outside [1, PMG_BATCH_MAX], NULL or repeated problems, a problem
+ * without pmg_device_init or on another device), UNSUPPORTED (2D, general path, or a
+ * p-hierarchy other than the paper's). */
 int pmg_batch_create(pmg_problem *const *problems, int n, const char *tuning_cache_path, pmg_batch **out);
 
 /* Launches and stages of one V-cycle of the batch in mg_prec (for inspection). */

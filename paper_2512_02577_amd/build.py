@@ -47,14 +47,17 @@ def _run(cmd: list[str]) -> None:
         raise RuntimeError(f"command failed ({res.returncode}): {' '.join(cmd)}\n{err}")
 
 
-def build_hip(jobs: int = 8) -> str:
+def build_hip(jobs: int = 8, only: list[str] | None = None) -> str:
+    """Compiles every source (or, with `only`, just those, reusing the other objects of
+    an earlier build) and links libpmg.so."""
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
     cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src in ("capi.cpp", "batch_host.cpp", "kernels_dispatch.cpp") else []
-        cmds.append([hipcc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
+        if only is None or src in only or not os.path.exists(obj):
+            cmds.append([hipcc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(cmds)))) as ex:
         list(ex.map(_run, cmds))
@@ -83,8 +86,9 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--asan", action="store_true")
     ap.add_argument("--jobs", type=int, default=8)
+    ap.add_argument("--only", nargs="*", help="recompile only these sources (file names under csrc/)")
     args = ap.parse_args(argv)
-    print(build_hip(args.jobs))
+    print(build_hip(args.jobs, args.only))
     print(build_emulation(args.asan))
     return 0
 

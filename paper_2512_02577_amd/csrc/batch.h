@@ -1,8 +1,10 @@
 // Batched stages: many independent Cartesian 3D problems (different sizes and degrees)
-// advance through one V-cycle stage in a single launch.  Each stage carries a table of
-// up to kBatchMax segments in its kernel arguments; a fixed (persistent) grid of
-// workgroups walks the concatenated work items of all segments and dispatches each item
-// to the body compiled for its segment's degree (paper p-hierarchy).
+// advance through one V-cycle stage together.  A stage table in device memory (read
+// through the constant address space) lists up to kBatchMax segments, one per problem;
+// a persistent grid of workgroups walks the concatenated work items (patches, tiles,
+// nodes) of all segments.  Patch and apply kernels exist once per degree, shaped like
+// the single-problem kernels of that degree (paper p-hierarchy), so a stage with several
+// degrees is one launch per degree, the launches independent of each other.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,8 +16,7 @@
 namespace pmg {
 
 constexpr int kBatchMax = 16;
-constexpr int batch_class(int p) { return p <= 4 ? 0 : (p <= 6 ? 1 : 2); }
-constexpr int kBatchThreads = 256;  // workgroup size of every batched workgroup kernel
+constexpr int kBatchThreads = 256;  // workgroup size of the batched transfer kernel
 
 // Apply tile (cells per direction) of option `opt` for degree p: 0 is the default of the
 // single-problem kernel, 1 one cell fewer (smaller LDS tile, more workgroups per CU).
@@ -112,9 +113,10 @@ template <typename T>
 struct BatchLaunch {
   static size_t smooth_bytes(int p);
   static size_t apply_bytes(int p, int tile);
-  // cls: register class of the degrees in the stage table, 0: p <= 4, 1: p in {5, 6}, 2: p >= 7
-  static int smooth(const BSmoothStage<T> *st_dev, int cls, int grid, size_t shmem, hipStream_t s);
-  static int apply(const BApplyStage<T> *st_dev, int cls, bool resid, int grid, size_t shmem, hipStream_t s);
+  // every segment of a smooth or apply stage table has degree p (one kernel per degree,
+  // shaped like the single-problem kernel of that degree); tile: batch_tile option
+  static int smooth(const BSmoothStage<T> *st_dev, int p, int grid, size_t shmem, hipStream_t s);
+  static int apply(const BApplyStage<T> *st_dev, int p, int tile, bool resid, int grid, size_t shmem, hipStream_t s);
   static int pass(const BPassStage<T> *st_dev, int grid, hipStream_t s);
   static int coarse(const BCoarseStage<T> *st_dev, int nseg, hipStream_t s);
   static int elem(const BElemStage *st_dev, int grid, hipStream_t s);

@@ -24,63 +24,40 @@ __device__ inline int seg_of(const cptr<Stage> &st, int nseg, long item) {
   return s;
 }
 
-// PLO..PHI: the degrees compiled into this kernel (one register class).
-template <typename T, int PLO, int PHI>
-__global__ __launch_bounds__(kBatchThreads) void k_bsmooth(const BSmoothStage<T> *st_) {
+// One kernel per degree: the patch body of the single-problem kernel (same threads per
+// workgroup, same registers) inside a loop over the work items of every segment.
+template <typename T, int P>
+__global__ __launch_bounds__(patch_threads(P)) void k_bsmooth(const BSmoothStage<T> *st_) {
+  using B = PatchBody<3, T, patch_threads(P), P, typename PaperH<P>::type>;
   const cptr<BSmoothStage<T>> st = as_const(st_);
   T *lds = lds_arena<T>();
   const int nseg = st->nseg, total = st->total;
   for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
     const int s = seg_of(st, nseg, blk);
     if (!as_const(st->active)[st->seg[s].prob]) continue;
+    const int local = blk - st->seg[s].start;
+    if (local >= st->seg[s].a.n_patch) continue;  // padding of the segment to a multiple of 8
     SmoothArgs<T> a;
     a = st->seg[s].a;
-    const int local = blk - st->seg[s].start;
-    switch (st->seg[s].p) {
-#define PMG_BS(P)                                                                                            \
-  case P:                                                                                                    \
-    if constexpr (P >= PLO && P <= PHI)                                                                      \
-      PatchBody<3, T, kBatchThreads, P, typename PaperH<P>::type>::smooth_patch(threadIdx.x, local, lds, a); \
-    break;
-      PMG_BS(1) PMG_BS(2) PMG_BS(3) PMG_BS(4) PMG_BS(5) PMG_BS(6) PMG_BS(7) PMG_BS(8)
-#undef PMG_BS
-      default:
-        break;
-    }
+    B::smooth_patch(threadIdx.x, local, lds, a);
     __syncthreads();
   }
 }
 
 template <typename T, int P, int OPT, bool RESID>
-__device__ inline void apply_tile(int local, T *lds, const ApplyArgs<T> &a) {
-  if constexpr (OPT == 0 || batch_tile(P, 1) != batch_tile(P, 0))
-    ApplyBody<3, T, kBatchThreads, P, batch_tile(P, OPT), RESID>::run(threadIdx.x, local, lds, a);
-}
-
-template <typename T, int PLO, int PHI, bool RESID>
-__global__ __launch_bounds__(kBatchThreads) void k_bapply(const BApplyStage<T> *st_) {
+__global__ __launch_bounds__(apply_threads(P)) void k_bapply(const BApplyStage<T> *st_) {
+  using B = ApplyBody<3, T, apply_threads(P), P, batch_tile(P, OPT), RESID>;
   const cptr<BApplyStage<T>> st = as_const(st_);
   T *lds = lds_arena<T>();
   const int nseg = st->nseg, total = st->total;
   for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
     const int s = seg_of(st, nseg, blk);
     if (!as_const(st->active)[st->seg[s].prob]) continue;
+    const int local = blk - st->seg[s].start;
+    if (local >= st->seg[s].a.n_tiles) continue;  // padding of the segment to a multiple of 8
     ApplyArgs<T> a;
     a = st->seg[s].a;
-    const int local = blk - st->seg[s].start;
-    switch (st->seg[s].p * 2 + st->seg[s].tile) {
-#define PMG_BA(P)                                                     \
-  case 2 * P:                                                         \
-    if constexpr (P >= PLO && P <= PHI) apply_tile<T, P, 0, RESID>(local, lds, a); \
-    break;                                                            \
-  case 2 * P + 1:                                                     \
-    if constexpr (P >= PLO && P <= PHI) apply_tile<T, P, 1, RESID>(local, lds, a); \
-    break;
-      PMG_BA(1) PMG_BA(2) PMG_BA(3) PMG_BA(4) PMG_BA(5) PMG_BA(6) PMG_BA(7) PMG_BA(8)
-#undef PMG_BA
-      default:
-        break;
-    }
+    B::run(threadIdx.x, local, lds, a);
     __syncthreads();
   }
 }
@@ -163,7 +140,7 @@ struct SmoothBytes {
   template <int P>
   struct F {
     static int run(size_t *o) {
-      *o = PatchBody<3, T, kBatchThreads, P, typename PaperH<P>::type>::size * sizeof(T);
+      *o = PatchBody<3, T, patch_threads(P), P, typename PaperH<P>::type>::size * sizeof(T);
       return 0;
     }
   };
@@ -174,8 +151,8 @@ struct ApplyBytes {
   template <int P>
   struct F {
     static int run(int opt, size_t *o) {
-      *o = (opt == 0 ? ApplyBody<3, T, kBatchThreads, P, batch_tile(P, 0), false>::size
-                     : ApplyBody<3, T, kBatchThreads, P, batch_tile(P, 1), false>::size) *
+      *o = (opt == 0 ? ApplyBody<3, T, apply_threads(P), P, batch_tile(P, 0), false>::size
+                     : ApplyBody<3, T, apply_threads(P), P, batch_tile(P, 1), false>::size) *
            sizeof(T);
       return 0;
     }
@@ -294,51 +271,55 @@ size_t BatchLaunch<T>::apply_bytes(int p, int tile) {
   return dispatch_degree<ApplyBytes<T>::template F>(p, tile, &o) == 0 ? o : 0;
 }
 
+// Kernel addresses by degree (and tile option, residual mode).
+template <typename T>
+struct KernelTable {
+  template <int P>
+  struct F {
+    static int run(const void **sm, const void **ap) {
+      *sm = (const void *)k_bsmooth<T, P>;
+      ap[0] = (const void *)k_bapply<T, P, 0, false>;
+      ap[1] = (const void *)k_bapply<T, P, 0, true>;
+      ap[2] = (const void *)k_bapply<T, P, 1, false>;
+      ap[3] = (const void *)k_bapply<T, P, 1, true>;
+      return 0;
+    }
+  };
+};
+
 template <typename T>
 int BatchLaunch<T>::prepare(size_t shmem) {
   if (shmem <= 65536) return 0;
-  const void *ks[] = {(const void *)k_bsmooth<T, 1, 4>,        (const void *)k_bsmooth<T, 5, 6>,
-                      (const void *)k_bsmooth<T, 7, 8>,        (const void *)k_bapply<T, 1, 4, true>,
-                      (const void *)k_bapply<T, 5, 6, true>,   (const void *)k_bapply<T, 7, 8, true>,
-                      (const void *)k_bapply<T, 1, 4, false>,  (const void *)k_bapply<T, 5, 6, false>,
-                      (const void *)k_bapply<T, 7, 8, false>};
-  for (const void *k : ks)
-    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess) return -4;
+  for (int p = 1; p <= kMaxDegree; ++p) {
+    const void *sm = nullptr, *ap[4] = {};
+    if (dispatch_degree<KernelTable<T>::template F>(p, &sm, ap) != 0) return -2;
+    for (const void *k : {sm, ap[0], ap[1], ap[2], ap[3]})
+      if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess) return -4;
+  }
   return 0;
 }
 
-
 template <typename T>
-int BatchLaunch<T>::smooth(const BSmoothStage<T> *st, int cls, int grid, size_t shmem, hipStream_t s) {
+int BatchLaunch<T>::smooth(const BSmoothStage<T> *st, int p, int grid, size_t shmem, hipStream_t s) {
   if (grid <= 0) return 0;
-  if (cls == 0)
-    hipLaunchKernelGGL((k_bsmooth<T, 1, 4>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-  else if (cls == 1)
-    hipLaunchKernelGGL((k_bsmooth<T, 5, 6>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-  else
-    hipLaunchKernelGGL((k_bsmooth<T, 7, 8>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-  return ok();
+  const void *sm = nullptr, *ap[4] = {};
+  if (dispatch_degree<KernelTable<T>::template F>(p, &sm, ap) != 0) return -2;
+  void *args[] = {(void *)&st};
+  if (hipLaunchKernel(sm, dim3(grid), dim3(patch_threads(p)), args, shmem, s) != hipSuccess) return -4;
+  return 0;
 }
 
 template <typename T>
-int BatchLaunch<T>::apply(const BApplyStage<T> *st, int cls, bool resid, int grid, size_t shmem, hipStream_t s) {
+int BatchLaunch<T>::apply(const BApplyStage<T> *st, int p, int tile, bool resid, int grid, size_t shmem,
+                          hipStream_t s) {
   if (grid <= 0) return 0;
-  if (resid) {
-    if (cls == 0)
-      hipLaunchKernelGGL((k_bapply<T, 1, 4, true>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-    else if (cls == 1)
-      hipLaunchKernelGGL((k_bapply<T, 5, 6, true>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-    else
-      hipLaunchKernelGGL((k_bapply<T, 7, 8, true>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-  } else {
-    if (cls == 0)
-      hipLaunchKernelGGL((k_bapply<T, 1, 4, false>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-    else if (cls == 1)
-      hipLaunchKernelGGL((k_bapply<T, 5, 6, false>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-    else
-      hipLaunchKernelGGL((k_bapply<T, 7, 8, false>), dim3(grid), dim3(kBatchThreads), shmem, s, st);
-  }
-  return ok();
+  const void *sm = nullptr, *ap[4] = {};
+  if (dispatch_degree<KernelTable<T>::template F>(p, &sm, ap) != 0) return -2;
+  void *args[] = {(void *)&st};
+  if (hipLaunchKernel(ap[2 * (tile != 0) + (resid ? 1 : 0)], dim3(grid), dim3(apply_threads(p)), args, shmem, s) !=
+      hipSuccess)
+    return -4;
+  return 0;
 }
 
 template <typename T>

@@ -27,14 +27,14 @@ using namespace pmg;
 
 namespace {
 
-constexpr int kClasses = 3;
+constexpr int kLanes = kMaxDegree;  // independent launches of one stage: one per degree
 
 enum Kind { K_SMOOTH = 0, K_APPLY, K_PASS, K_COARSE, K_ELEM };
 
 // One launch.  Consecutive steps with the same group touch disjoint problems and may run
 // concurrently.
 struct Step {
-  int kind = 0, cls = 0, resid = 0, group = 0;
+  int kind = 0, p = 0, tile = 0, resid = 0, group = 0;  // p: degree of smooth and apply steps
   size_t off = 0;    // byte offset of the stage table in the plan's device buffer
   long items = 0;    // workgroups of work: patches, tiles, or 256-thread blocks
   size_t shmem = 0;  // dynamic LDS of the launch
@@ -42,10 +42,11 @@ struct Step {
 };
 
 // Launch parameters of one plan: persistent workgroups per compute unit of each kernel
-// (0: one workgroup per work item) and the apply tile option of each degree.
+// (0: one workgroup per work item) and the apply tile option, per degree.
 struct Tuning {
-  int smooth_wpc[kClasses] = {2, 2, 1};
-  int apply_wpc[kClasses] = {0, 0, 0};
+  int lanes = 1;  // 1: the launches of one stage run as parallel branches, 0: one after another
+  int smooth_wpc[kMaxDegree + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int apply_wpc[kMaxDegree + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   int pass_wpc = 0, elem_wpc = 0;
   int tile[kMaxDegree + 1] = {};
 };
@@ -53,6 +54,7 @@ struct Tuning {
 template <typename T>
 struct Plan {
   bool supported = false;
+  bool pending = false;  // some launch parameter still has to be measured
   std::vector<Step> steps;
   std::vector<unsigned char> blob;  // host image of the stage tables
   unsigned char *dev = nullptr;     // device copy
@@ -68,6 +70,7 @@ struct pmg_batch {
   int n = 0, device = -1, ncu = 256;
   size_t lds_max = 0;
   std::string arch, cache_path;
+  std::map<std::string, int> cache;  // launch parameters by "arch/3d/precision/knob"
   std::vector<pmg_problem *> pr;
   Plan<double> p64;   // multigrid in float64
   Plan<float> p32;    // multigrid in float32
@@ -80,8 +83,8 @@ struct pmg_batch {
   double *part = nullptr, *scal = nullptr, *hscal = nullptr;
   BVecStage *vec = nullptr, *hvec = nullptr;  // outer CG vector table, device and pinned
   int vec_blocks = 0;
-  hipStream_t cs = nullptr, aux[kClasses - 1] = {nullptr, nullptr};
-  hipEvent_t ev_fork = nullptr, ev_join[kClasses - 1] = {nullptr, nullptr}, t0 = nullptr, t1 = nullptr;
+  hipStream_t cs = nullptr, aux[kLanes - 1] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kLanes - 1] = {}, t0 = nullptr, t1 = nullptr;
 };
 
 namespace {
@@ -145,6 +148,11 @@ size_t used_bytes(int nseg) {
 
 long round256(long x) { return (x + 255) / 256 * 256; }
 
+// Work items of a segment start at a multiple of 8: with a grid that is a multiple of 8,
+// work item i then runs on XCD i mod 8 as in a single-problem launch, which is what the
+// XCD-aware patch and tile order of the kernel bodies assumes.
+int round8(int x) { return (x + 7) / 8 * 8; }
+
 // ---- plan construction ----
 template <typename T>
 struct Builder {
@@ -152,10 +160,11 @@ struct Builder {
   Plan<T> &pl;
   int group = 0;
 
-  void push(int kind, int cls, int resid, size_t off, long items, size_t shmem) {
+  void push(int kind, int p, int tile, int resid, size_t off, long items, size_t shmem) {
     Step s;
     s.kind = kind;
-    s.cls = cls;
+    s.p = p;
+    s.tile = tile;
     s.resid = resid;
     s.group = group;
     s.off = off;
@@ -193,18 +202,17 @@ struct Builder {
     }
     if (!st.nseg) return;
     st.total = tot;
-    push(K_ELEM, 0, 0, put(pl.blob, st, used_bytes<BElemStage, BElemSeg>(st.nseg)), tot / 256, 0);
+    push(K_ELEM, 0, 0, 0, put(pl.blob, st, used_bytes<BElemStage, BElemSeg>(st.nseg)), tot / 256, 0);
     ++group;
   }
 
-  // one color sweep stage; dir > 0 ascending colors
+  // one color sweep stage over the listed (problem, level) pairs
   void smooth(const std::vector<std::pair<int, int>> &parts, int col) {
-    BSmoothStage<T> st[kClasses]{};
-    int tot[kClasses] = {0, 0, 0};
-    size_t sh[kClasses] = {0, 0, 0};
+    BSmoothStage<T> st[kLanes + 1]{};
+    int tot[kLanes + 1] = {};
     for (auto [i, l] : parts) {
       pmg_problem *pr = bt->pr[i];
-      const int n = pr->sizes[l], cls = batch_class(pr->p);
+      const int n = pr->sizes[l], p = pr->p;
       SmoothArgs<T> a{};
       a.tb = pr->pd<T>().tabs;
       a.c = (T)pr->cscale(l);
@@ -221,20 +229,20 @@ struct Builder {
         a.n_patch *= a.cnt[d];
       }
       if (a.n_patch == 0) continue;
-      BSmoothSeg<T> &g = st[cls].seg[st[cls].nseg++];
-      g.start = tot[cls];
-      g.p = pr->p;
+      BSmoothSeg<T> &g = st[p].seg[st[p].nseg++];
+      g.start = tot[p];
+      g.p = p;
       g.prob = i;
       g.a = a;
-      tot[cls] += a.n_patch;
-      sh[cls] = std::max(sh[cls], BatchLaunch<T>::smooth_bytes(pr->p));
+      tot[p] += round8(a.n_patch);
     }
     bool any = false;
-    for (int c = 0; c < kClasses; ++c) {
-      if (!st[c].nseg) continue;
-      st[c].total = tot[c];
-      st[c].active = bt->active;
-      push(K_SMOOTH, c, 0, put(pl.blob, st[c], used_bytes<BSmoothStage<T>, BSmoothSeg<T>>(st[c].nseg)), tot[c], sh[c]);
+    for (int p = 1; p <= kLanes; ++p) {
+      if (!st[p].nseg) continue;
+      st[p].total = tot[p];
+      st[p].active = bt->active;
+      push(K_SMOOTH, p, 0, 0, put(pl.blob, st[p], used_bytes<BSmoothStage<T>, BSmoothSeg<T>>(st[p].nseg)), tot[p],
+           BatchLaunch<T>::smooth_bytes(p));
       any = true;
     }
     if (any) ++group;
@@ -243,12 +251,11 @@ struct Builder {
   // operator apply on h-level l of each listed problem: residual (out = t_l = R - A Z) in
   // the V-cycle, or q = A p of the outer CG
   void apply(const std::vector<std::pair<int, int>> &parts, bool resid) {
-    BApplyStage<T> st[kClasses]{};
-    int tot[kClasses] = {0, 0, 0};
-    size_t sh[kClasses] = {0, 0, 0};
+    BApplyStage<T> st[kLanes + 1]{};
+    int tot[kLanes + 1] = {};
     for (auto [i, l] : parts) {
       pmg_problem *pr = bt->pr[i];
-      const int p = pr->p, cls = batch_class(p), opt = pl.tune.tile[p];
+      const int p = pr->p, opt = pl.tune.tile[p];
       const int tc = batch_tile(p, opt);
       ApplyArgs<T> a{};
       a.Kt = opt ? alt_kt<T>(bt, i) : pr->pd<T>().tabs.Kt;
@@ -266,23 +273,23 @@ struct Builder {
         a.b = nullptr;
         a.out = pr->fq;
       }
-      BApplySeg<T> &g = st[cls].seg[st[cls].nseg++];
-      g.start = tot[cls];
+      BApplySeg<T> &g = st[p].seg[st[p].nseg++];
+      g.start = tot[p];
       g.p = p;
       g.prob = i;
       g.tile = opt;
       g.a = a;
-      tot[cls] += a.n_tiles;
-      sh[cls] = std::max(sh[cls], BatchLaunch<T>::apply_bytes(p, opt));
+      tot[p] += round8(a.n_tiles);
     }
     bool any = false;
-    for (int c = 0; c < kClasses; ++c) {
-      if (!st[c].nseg) continue;
-      st[c].total = tot[c];
-      st[c].resid = resid;
-      st[c].active = bt->active;
-      push(K_APPLY, c, resid, put(pl.blob, st[c], used_bytes<BApplyStage<T>, BApplySeg<T>>(st[c].nseg)), tot[c],
-           sh[c]);
+    for (int p = 1; p <= kLanes; ++p) {
+      if (!st[p].nseg) continue;
+      st[p].total = tot[p];
+      st[p].resid = resid;
+      st[p].active = bt->active;
+      push(K_APPLY, p, pl.tune.tile[p], resid,
+           put(pl.blob, st[p], used_bytes<BApplyStage<T>, BApplySeg<T>>(st[p].nseg)), tot[p],
+           BatchLaunch<T>::apply_bytes(p, pl.tune.tile[p]));
       any = true;
     }
     if (any) ++group;
@@ -319,7 +326,8 @@ struct Builder {
     for (int k = 0; k < 3; ++k) {
       st[k].total_threads = thr[k];
       st[k].active = bt->active;
-      push(K_PASS, 0, 0, put(pl.blob, st[k], used_bytes<BPassStage<T>, BPassSeg<T>>(st[k].nseg)), thr[k] / 256, 0);
+      push(K_PASS, 0, 0, 0, put(pl.blob, st[k], used_bytes<BPassStage<T>, BPassSeg<T>>(st[k].nseg)), thr[k] / 256,
+           0);
       ++group;
     }
   }
@@ -342,7 +350,7 @@ struct Builder {
       st.prob[st.nseg] = i;
       st.seg[st.nseg++] = a;
     }
-    push(K_COARSE, 0, 0, put(pl.blob, st, used_bytes<BCoarseStage<T>, CoarseArgs<T>>(st.nseg)), st.nseg, 0);
+    push(K_COARSE, 0, 0, 0, put(pl.blob, st, used_bytes<BCoarseStage<T>, CoarseArgs<T>>(st.nseg)), st.nseg, 0);
     ++group;
   }
 };
@@ -414,14 +422,14 @@ void size_grids(pmg_batch *bt, Plan<T> &pl) {
   for (Step &s : pl.steps) {
     int wpc = 0;
     switch (s.kind) {
-      case K_SMOOTH: wpc = pl.tune.smooth_wpc[s.cls]; break;
-      case K_APPLY: wpc = pl.tune.apply_wpc[s.cls]; break;
+      case K_SMOOTH: wpc = pl.tune.smooth_wpc[s.p]; break;
+      case K_APPLY: wpc = pl.tune.apply_wpc[s.p]; break;
       case K_PASS: wpc = pl.tune.pass_wpc; break;
       case K_ELEM: wpc = pl.tune.elem_wpc; break;
       default: wpc = 0;
     }
     long g = s.items;
-    if (wpc > 0) g = std::min(g, (long)wpc * bt->ncu);
+    if (wpc > 0) g = std::min(g, (long)wpc * bt->ncu / 8 * 8);
     s.grid = (int)std::max(1L, g);
   }
 }
@@ -465,8 +473,9 @@ template <typename T>
 int launch_step(const Plan<T> &pl, const Step &s, hipStream_t st) {
   const void *tab = pl.dev + s.off;
   switch (s.kind) {
-    case K_SMOOTH: return BatchLaunch<T>::smooth((const BSmoothStage<T> *)tab, s.cls, s.grid, s.shmem, st);
-    case K_APPLY: return BatchLaunch<T>::apply((const BApplyStage<T> *)tab, s.cls, s.resid, s.grid, s.shmem, st);
+    case K_SMOOTH: return BatchLaunch<T>::smooth((const BSmoothStage<T> *)tab, s.p, s.grid, s.shmem, st);
+    case K_APPLY:
+      return BatchLaunch<T>::apply((const BApplyStage<T> *)tab, s.p, s.tile, s.resid, s.grid, s.shmem, st);
     case K_PASS: return BatchLaunch<T>::pass((const BPassStage<T> *)tab, s.grid, st);
     case K_COARSE: return BatchLaunch<T>::coarse((const BCoarseStage<T> *)tab, s.grid, st);
     default: return BatchLaunch<T>::elem((const BElemStage *)tab, s.grid, st);
@@ -486,9 +495,9 @@ int run_steps(pmg_batch *bt, const Plan<T> &pl, hipStream_t st, const std::funct
       if (!keep || keep(v[j])) grp.push_back(&v[j]);
       ++j;
     }
-    if (grp.size() == 1) {
-      PMG_TRY(launch_step(pl, *grp[0], st));
-    } else if (grp.size() > 1) {
+    if (grp.size() == 1 || !pl.tune.lanes) {
+      for (const Step *g : grp) PMG_TRY(launch_step(pl, *g, st));
+    } else {
       PMG_HIP(hipEventRecord(bt->ev_fork, st));
       for (size_t k = 1; k < grp.size(); ++k) {
         PMG_HIP(hipStreamWaitEvent(bt->aux[k - 1], bt->ev_fork, 0));
@@ -550,17 +559,17 @@ int ensure_graphs(pmg_batch *bt, Plan<T> &pl) {
 }
 
 // ---- tuner ----
-// Average time of the selected steps (3 runs after one warm-up run), in ms.
+// Average time of the selected steps (2 runs after one warm-up run), in ms.
 template <typename T>
 float time_steps(pmg_batch *bt, Plan<T> &pl, const std::function<bool(const Step &)> &keep) {
   if (run_steps(bt, pl, bt->cs, keep) != PMG_OK) return 1e30f;
   if (hipEventRecord(bt->t0, bt->cs) != hipSuccess) return 1e30f;
-  for (int r = 0; r < 3; ++r)
+  for (int r = 0; r < 2; ++r)
     if (run_steps(bt, pl, bt->cs, keep) != PMG_OK) return 1e30f;
   if (hipEventRecord(bt->t1, bt->cs) != hipSuccess || hipEventSynchronize(bt->t1) != hipSuccess) return 1e30f;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, bt->t0, bt->t1) != hipSuccess) return 1e30f;
-  return ms / 3.f;
+  return ms / 2.f;
 }
 
 struct Knob {
@@ -571,35 +580,26 @@ struct Knob {
   bool tables;  // the knob changes stage tables (apply tile)
 };
 
+// Every knob is judged by the time of the whole plan (the V-cycle, or the outer apply), so
+// that launches of other degrees running beside it count.
 template <typename T>
 std::vector<Knob> knobs(pmg_batch *bt, Plan<T> &pl, bool outer) {
   std::vector<Knob> k;
-  bool cls[kClasses] = {false, false, false}, deg[kMaxDegree + 1] = {};
-  for (pmg_problem *pr : bt->pr) {
-    cls[batch_class(pr->p)] = true;
-    deg[pr->p] = true;
-  }
-  const std::vector<int> wpc = {1, 2, 3, 4, 6, 8, 0};
-  for (int c = 0; c < kClasses; ++c) {
-    if (!cls[c]) continue;
-    if (!outer)
-      k.push_back({"smooth_wpc/c" + std::to_string(c), &pl.tune.smooth_wpc[c], wpc,
-                   [c](const Step &s) { return s.kind == K_SMOOTH && s.cls == c; }, false});
-    k.push_back({"apply_wpc/c" + std::to_string(c), &pl.tune.apply_wpc[c], wpc,
-                 [c](const Step &s) { return s.kind == K_APPLY && s.cls == c; }, false});
-  }
+  bool deg[kMaxDegree + 1] = {};
+  for (pmg_problem *pr : bt->pr) deg[pr->p] = true;
+  const std::vector<int> wpc = {0, 1, 2, 4, 8};
+  k.push_back({"lanes", &pl.tune.lanes, {1, 0}, nullptr, false});
   for (int p = 1; p <= kMaxDegree; ++p) {
-    if (!deg[p] || batch_tile(p, 1) == batch_tile(p, 0)) continue;
-    bool fits = BatchLaunch<T>::apply_bytes(p, 1) <= bt->lds_max;
-    if (!fits) continue;
-    k.push_back({"apply_tile/p" + std::to_string(p), &pl.tune.tile[p], {0, 1},
-                 [](const Step &s) { return s.kind == K_APPLY; }, true});
+    if (!deg[p]) continue;
+    const std::string d = "/p" + std::to_string(p);
+    if (!outer) k.push_back({"smooth_wpc" + d, &pl.tune.smooth_wpc[p], wpc, nullptr, false});
+    if (batch_tile(p, 1) != batch_tile(p, 0) && BatchLaunch<T>::apply_bytes(p, 1) <= bt->lds_max)
+      k.push_back({"apply_tile" + d, &pl.tune.tile[p], {0, 1}, nullptr, true});
+    k.push_back({"apply_wpc" + d, &pl.tune.apply_wpc[p], wpc, nullptr, false});
   }
   if (!outer) {
-    k.push_back({"pass_wpc", &pl.tune.pass_wpc, {2, 4, 8, 16, 0}, [](const Step &s) { return s.kind == K_PASS; },
-                 false});
-    k.push_back({"elem_wpc", &pl.tune.elem_wpc, {2, 4, 8, 16, 0}, [](const Step &s) { return s.kind == K_ELEM; },
-                 false});
+    k.push_back({"pass_wpc", &pl.tune.pass_wpc, {0, 4, 16}, nullptr, false});
+    k.push_back({"elem_wpc", &pl.tune.elem_wpc, {0, 4, 16}, nullptr, false});
   }
   return k;
 }
@@ -642,24 +642,29 @@ int write_cache(const std::string &path, const std::map<std::string, int> &m) {
   return PMG_OK;
 }
 
-// Takes each knob's value from the cache, or measures its candidates one knob at a time
-// (coordinate descent in the order of `knobs`) and records the best.
+// Takes each knob's value from the cache; with `measure`, times the candidates of the
+// knobs the cache lacks, one knob at a time (coordinate descent in the order of `knobs`),
+// and records the best.  Otherwise a missing knob keeps its default and the plan stays
+// pending.  Measuring runs the plan on the problems' work buffers, zeroed first.
 template <typename T>
-int tune(pmg_batch *bt, Plan<T> &pl, const std::string &prefix, bool outer, std::map<std::string, int> &cache,
-         bool *changed) {
+int tune(pmg_batch *bt, Plan<T> &pl, const std::string &prefix, bool outer, bool measure) {
   std::vector<Knob> ks = knobs(bt, pl, outer);
-  bool tables = false;
   std::vector<Knob *> todo;
   for (Knob &k : ks) {
-    auto it = cache.find(prefix + k.key);
-    if (it != cache.end() && std::find(k.cand.begin(), k.cand.end(), it->second) != k.cand.end()) {
+    auto it = bt->cache.find(prefix + k.key);
+    if (it != bt->cache.end() && std::find(k.cand.begin(), k.cand.end(), it->second) != k.cand.end())
       *k.val = it->second;
-      tables = tables || k.tables;
-    } else {
+    else
       todo.push_back(&k);
-    }
   }
   if (int rc = upload(bt, pl, outer)) return rc;
+  pl.pending = !todo.empty();
+  if (!measure || todo.empty()) return PMG_OK;
+  for (pmg_problem *pr : bt->pr) {
+    const size_t N = (size_t)pr->nodes(pr->finest());
+    PMG_HIP(hipMemsetAsync(pr->fr[0], 0, N * sizeof(double), bt->cs));
+    PMG_HIP(hipMemsetAsync(pr->fp, 0, N * sizeof(double), bt->cs));
+  }
   for (Knob *k : todo) {
     int best = *k->val;
     float tbest = 1e30f;
@@ -682,12 +687,18 @@ int tune(pmg_batch *bt, Plan<T> &pl, const std::string &prefix, bool outer, std:
     } else {
       size_grids(bt, pl);
     }
-    cache[prefix + k->key] = best;
-    *changed = true;
+    bt->cache[prefix + k->key] = best;
   }
-  (void)tables;
   PMG_HIP(hipStreamSynchronize(bt->cs));
-  return PMG_OK;
+  pl.pending = false;
+  return write_cache(bt->cache_path, bt->cache);
+}
+
+// Before the first use of a plan: measure the knobs its cache entries lack.
+template <typename T>
+int ready(pmg_batch *bt, Plan<T> &pl, const char *prec, bool outer) {
+  if (!pl.pending || bt->cache_path.empty()) return PMG_OK;
+  return tune(bt, pl, bt->arch + "/3d/" + prec + "/", outer, true);
 }
 
 int check_mg(pmg_batch *bt, int mg_prec) {
@@ -706,9 +717,12 @@ void destroy(pmg_batch *bt) {
   if (bt->hactive) (void)hipHostFree(bt->hactive);
   if (bt->hscal) (void)hipHostFree(bt->hscal);
   if (bt->hvec) (void)hipHostFree(bt->hvec);
-  for (hipStream_t s : {bt->cs, bt->aux[0], bt->aux[1]})
+  if (bt->cs) (void)hipStreamDestroy(bt->cs);
+  for (hipStream_t s : bt->aux)
     if (s) (void)hipStreamDestroy(s);
-  for (hipEvent_t e : {bt->ev_fork, bt->ev_join[0], bt->ev_join[1], bt->t0, bt->t1})
+  for (hipEvent_t e : bt->ev_join)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {bt->ev_fork, bt->t0, bt->t1})
     if (e) (void)hipEventDestroy(e);
   delete bt;
 }
@@ -813,28 +827,15 @@ int create(pmg_batch *bt, pmg_problem *const *problems, int n, const char *path)
   for (int i = 0; i < n; ++i) bt->hactive[i] = 1;
   PMG_HIP(hipMemcpy(bt->active, bt->hactive, (size_t)n * sizeof(int), hipMemcpyHostToDevice));
   PMG_HIP(hipMemcpy(bt->vec, bt->hvec, sizeof(BVecStage), hipMemcpyHostToDevice));
-  // plans and their launch parameters; the tuner runs on zeroed inputs
-  if (path) bt->cache_path = path;
-  for (pmg_problem *pr : bt->pr) {
-    const size_t N = (size_t)pr->nodes(pr->finest());
-    PMG_HIP(hipMemsetAsync(pr->fr[0], 0, N * sizeof(double), bt->cs));
-    PMG_HIP(hipMemsetAsync(pr->fp, 0, N * sizeof(double), bt->cs));
-  }
-  PMG_HIP(hipStreamSynchronize(bt->cs));
-  std::map<std::string, int> cache;
-  if (path) cache = read_cache(bt->cache_path);
-  bool changed = false;
-  const std::string pre = bt->arch + "/3d/";
+  // plans with the cached launch parameters (defaults where the cache has none)
   if (path) {
-    if (bt->p64.supported && (rc = tune(bt, bt->p64, pre + "fp64/", false, cache, &changed))) return rc;
-    if ((rc = tune(bt, bt->p32, pre + "fp32/", false, cache, &changed))) return rc;
-    if ((rc = tune(bt, bt->outer, pre + "fp64-outer/", true, cache, &changed))) return rc;
-    if (changed && (rc = write_cache(bt->cache_path, cache))) return rc;
-  } else {
-    if (bt->p64.supported && (rc = upload(bt, bt->p64, false))) return rc;
-    if ((rc = upload(bt, bt->p32, false))) return rc;
-    if ((rc = upload(bt, bt->outer, true))) return rc;
+    bt->cache_path = path;
+    bt->cache = read_cache(bt->cache_path);
   }
+  const std::string pre = bt->arch + "/3d/";
+  if (bt->p64.supported && (rc = tune(bt, bt->p64, pre + "fp64/", false, false))) return rc;
+  if ((rc = tune(bt, bt->p32, pre + "fp32/", false, false))) return rc;
+  if ((rc = tune(bt, bt->outer, pre + "fp64-outer/", true, false))) return rc;
   return PMG_OK;
 }
 
@@ -892,8 +893,8 @@ int pmg_batch_vcycle(pmg_batch *bt, int mg_prec, const double *const *r, double 
   for (int i = 0; i < bt->n; ++i)
     if (!r[i] || !z[i]) return fail(PMG_ERR_INVALID_ARG, "r[%d] or z[%d] is NULL", i, i);
   hipStream_t s = (hipStream_t)stream;
-  int rc = mg_prec == PMG_FP64 ? ensure_graphs(bt, bt->p64) : ensure_graphs(bt, bt->p32);
-  if (rc) return rc;
+  int rc = mg_prec == PMG_FP64 ? ready(bt, bt->p64, "fp64", false) : ready(bt, bt->p32, "fp32", false);
+  if (rc || (rc = mg_prec == PMG_FP64 ? ensure_graphs(bt, bt->p64) : ensure_graphs(bt, bt->p32))) return rc;
   for (int i = 0; i < bt->n; ++i) bt->hactive[i] = 1;
   PMG_HIP(hipMemcpyAsync(bt->active, bt->hactive, (size_t)bt->n * sizeof(int), hipMemcpyHostToDevice, s));
   for (int i = 0; i < bt->n; ++i) {
@@ -917,8 +918,9 @@ int pmg_batch_solve(pmg_batch *bt, int mg_prec, const double *const *b, double *
   for (int i = 0; i < bt->n; ++i)
     if (!b[i] || !x[i]) return fail(PMG_ERR_INVALID_ARG, "b[%d] or x[%d] is NULL", i, i);
   hipStream_t s = (hipStream_t)stream;
-  int rc = mg_prec == PMG_FP64 ? ensure_graphs(bt, bt->p64) : ensure_graphs(bt, bt->p32);
-  if (rc) return rc;
+  int rc = mg_prec == PMG_FP64 ? ready(bt, bt->p64, "fp64", false) : ready(bt, bt->p32, "fp32", false);
+  if (rc || (rc = ready(bt, bt->outer, "fp64-outer", true))) return rc;
+  if ((rc = mg_prec == PMG_FP64 ? ensure_graphs(bt, bt->p64) : ensure_graphs(bt, bt->p32))) return rc;
   hipGraphExec_t g = mg_prec == PMG_FP64 ? bt->p64.igraph : bt->p32.igraph;
   const int n = bt->n;
   // x = 0, r = rold = b, p = 0; rz = 1 so that the first beta is (z,r) - (z,r) = 0

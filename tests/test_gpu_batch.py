@@ -154,9 +154,9 @@ def test_batch_stats_and_rejections():
     probs = [make(4, 2), make(4, 5), make(4, 7)]
     bt = pmg.batch_create(probs)
     stages, launches = pmg.batch_stats(bt, pmg.FP32)
-    # 3 classes in every sweep and residual stage: more launches than stages
+    # one launch per degree in every sweep and residual stage: more launches than stages
     assert launches > stages > 0
-    one = pmg.batch_create([make(4, 3), make(8, 2)])
+    one = pmg.batch_create([make(4, 3), make(6, 3)])
     s1, l1 = pmg.batch_stats(one, pmg.FP64)
     assert s1 == l1
     p8 = pmg.batch_create([make(2, 8)])
@@ -179,21 +179,27 @@ def test_tuning_cache_written_and_reused(tmp_path):
     path = str(tmp_path / "tune.json")
     probs = [make(6, 2), make(4, 5), make(4, 3)]
     bt = pmg.batch_create(probs, path)
-    data = json.load(open(path))
-    keys = set(data)
-    assert any(k.endswith("fp32/smooth_wpc/c0") for k in keys) and any("fp64-outer/apply_wpc" in k for k in keys)
-    assert all(v in (0, 1, 2, 3, 4, 6, 8, 16) for v in data.values())
-    assert any("apply_tile/p5" in k for k in keys)
-    before = os.stat(path).st_mtime_ns
-    bt2 = pmg.batch_create(probs, path)
-    assert os.stat(path).st_mtime_ns == before
+    assert not os.path.exists(path)  # measured at the first use of a precision
     bs = [dev(rhs_vector(3, pr.cells[-1], pr.p, 9 + k)) for k, pr in enumerate(probs)]
     x1 = [torch.empty_like(b) for b in bs]
-    x2 = [torch.empty_like(b) for b in bs]
     i1 = pmg.batch_solve(bt, bs, x1, pmg.FP32)
+    data = json.load(open(path))
+    keys = set(data)
+    assert any(k.endswith("fp32/smooth_wpc/p2") for k in keys) and any("fp64-outer/apply_wpc/p5" in k for k in keys)
+    assert any(k.endswith("fp32/apply_tile/p5") for k in keys) and any(k.endswith("fp32/lanes") for k in keys)
+    assert not any("/fp64/" in k for k in keys)
+    assert all(v in (0, 1, 2, 4, 8, 16) for v in data.values())
+    before = os.stat(path).st_mtime_ns
+    bt2 = pmg.batch_create(probs, path)
+    x2 = [torch.empty_like(b) for b in bs]
     i2 = pmg.batch_solve(bt2, bs, x2, pmg.FP32)
+    assert os.stat(path).st_mtime_ns == before
     assert [i.iterations for i in i1] == [i.iterations for i in i2]
     assert all(i.rel_residual <= 1e-8 for i in i1 + i2)
+    z = [torch.empty_like(b) for b in bs]
+    pmg.batch_vcycle(bt2, bs, z, pmg.FP64)
+    torch.cuda.synchronize()
+    assert any("/fp64/" in k for k in json.load(open(path)))
 
 
 def test_full_size_16_problem_batch():
