@@ -111,7 +111,7 @@ template <> struct PaperH<8> { using type = Degrees<1, 3, 7, 8>; };
 // is created) and are read through the constant address space.
 template <typename T>
 struct BatchLaunch {
-  static size_t smooth_bytes(int p);
+  static size_t smooth_bytes(int p, int n_iter);  // dynamic LDS of the patch kernel
   static size_t apply_bytes(int p, int tile);
   // every segment of a smooth or apply stage table has degree p (one kernel per degree,
   // shaped like the single-problem kernel of that degree); tile: batch_tile option

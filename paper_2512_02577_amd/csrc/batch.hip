@@ -139,8 +139,8 @@ template <typename T>
 struct SmoothBytes {
   template <int P>
   struct F {
-    static int run(size_t *o) {
-      *o = PatchBody<3, T, patch_threads(P), P, typename PaperH<P>::type>::size * sizeof(T);
+    static int run(int n_iter, size_t *o) {
+      *o = PatchBody<3, T, patch_threads(P), P, typename PaperH<P>::type>::arena(n_iter) * sizeof(T);
       return 0;
     }
   };
@@ -260,9 +260,9 @@ __global__ __launch_bounds__(kT) void k_bvec_final(const BVecStage *st_, int op)
 }  // namespace
 
 template <typename T>
-size_t BatchLaunch<T>::smooth_bytes(int p) {
+size_t BatchLaunch<T>::smooth_bytes(int p, int n_iter) {
   size_t o = 0;
-  return dispatch_degree<SmoothBytes<T>::template F>(p, &o) == 0 ? o : 0;
+  return dispatch_degree<SmoothBytes<T>::template F>(p, n_iter, &o) == 0 ? o : 0;
 }
 
 template <typename T>

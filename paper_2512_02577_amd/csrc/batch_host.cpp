@@ -241,8 +241,10 @@ struct Builder {
       if (!st[p].nseg) continue;
       st[p].total = tot[p];
       st[p].active = bt->active;
+      int iters = 1;
+      for (int k = 0; k < st[p].nseg; ++k) iters = std::max(iters, st[p].seg[k].a.n_iter);
       push(K_SMOOTH, p, 0, 0, put(pl.blob, st[p], used_bytes<BSmoothStage<T>, BSmoothSeg<T>>(st[p].nseg)), tot[p],
-           BatchLaunch<T>::smooth_bytes(p));
+           BatchLaunch<T>::smooth_bytes(p, iters));
       any = true;
     }
     if (any) ++group;
@@ -756,10 +758,12 @@ int create(pmg_batch *bt, pmg_problem *const *problems, int n, const char *path)
   // which multigrid precisions fit: every patch and apply arena in LDS
   bt->p64.supported = bt->p32.supported = bt->outer.supported = true;
   for (pmg_problem *pr : bt->pr) {
-    if (BatchLaunch<double>::smooth_bytes(pr->p) > bt->lds_max ||
+    const int it = pr->cfg.n_local_iter;
+    if (BatchLaunch<double>::smooth_bytes(pr->p, it) > bt->lds_max ||
         BatchLaunch<double>::apply_bytes(pr->p, 0) > bt->lds_max)
       bt->p64.supported = false;
-    if (BatchLaunch<float>::smooth_bytes(pr->p) > bt->lds_max || BatchLaunch<float>::apply_bytes(pr->p, 0) > bt->lds_max)
+    if (BatchLaunch<float>::smooth_bytes(pr->p, it) > bt->lds_max ||
+        BatchLaunch<float>::apply_bytes(pr->p, 0) > bt->lds_max)
       bt->p32.supported = false;
     if (BatchLaunch<double>::apply_bytes(pr->p, 0) > bt->lds_max) bt->outer.supported = false;
   }

@@ -68,56 +68,56 @@ struct PatchBody {
   static constexpr int nl(int l) { return 2 * H::q[l] - 1; }
   static constexpr int ndl(int l) { return ipow(2 * H::q[l] - 1, DIM); }
 
-  // ---- LDS layout ----
-  // phase R (patch residual):  r | ucl (later stage-2 output) | stage-1 output
-  // phase S (local solve):     r | d | c | lower-level r_l, d_l | scratch X | scratch Y
-  // Scratch roles: a level vmult writes its stage-1 pair into X and stage-2 pair into Y;
-  // the result `res` goes to X in 3D (stage-1 pair is dead by then) and to Y in 2D; the
-  // transfer temporaries use Y in 3D and X in 2D.
-  using RS = LapScratch<DIM, N, n>;
-  static constexpr int R0 = cmax(Nd, RS::cg);
+  // ---- LDS layout (every contraction that shrinks a tensor runs in place) ----
+  // phase R (patch residual): r | closure tensor (stage outputs A, C in place) | B, G
+  // phase S (local solve):    r | d | partial sums | r_l, d_l of levels L-2 .. 1 | X (2 nd) | cc
+  // X holds a level's vmult pair (A, B; the residual lands on A in place), the in-place
+  // restriction of that residual, and the two stages of a prolongation.  cc (the
+  // correction of Richardson steps after the first) is at the end, so that one step
+  // needs only `size1`.
   static constexpr int off_r = 0;  // patch residual, then running Richardson residual
   static constexpr int off_ucl = nd;
-  static constexpr int off_abR = nd + R0;
-  static constexpr int phaseR_end = nd + R0 + RS::ab;
+  static constexpr int off_B = nd + Nd;
+  static constexpr int phaseR_end = off_B + (DIM == 3 ? n * N * N : n * N);
   static constexpr int off_d = nd;
-  static constexpr int off_cc = 2 * nd;
-  static constexpr int lower_size(int l) { return l < 0 ? 0 : 2 * ndl(l) + lower_size(l - 1); }
-  static constexpr int off_lr(int l) { return 3 * nd + (l == 0 ? 0 : lower_size(l - 1)); }
+  static constexpr int NRED = 4;  // per-wave partial sums of block_sum (up to 4 waves)
+  static constexpr int off_red = 2 * nd;
+  static constexpr int lower_size(int l) { return l <= 0 ? 0 : 2 * ndl(l) + lower_size(l - 1); }  // levels 1..l
+  static constexpr int off_lr(int l) { return 2 * nd + NRED + lower_size(l - 1); }
   static constexpr int off_ld(int l) { return off_lr(l) + ndl(l); }
-  static constexpr int level_x(int l) {  // scratch X need of level l (and its transfers)
-    return DIM == 3 ? lap_ab(DIM, nl(l), nl(l))
-                    : cmax(lap_ab(DIM, nl(l), nl(l)),
-                           l > 0 ? cmax(kron_t1(DIM, nl(l), nl(l - 1)), kron_t1(DIM, nl(l - 1), nl(l))) : 0);
-  }
-  static constexpr int level_y(int l) {
-    return DIM == 3 ? cmax(lap_cg(DIM, nl(l), nl(l)),
-                           l > 0 ? cmax(kron_t1(DIM, nl(l), nl(l - 1)) + kron_t2(DIM, nl(l), nl(l - 1)),
-                                        kron_t1(DIM, nl(l - 1), nl(l)) + kron_t2(DIM, nl(l - 1), nl(l)))
-                                 : 0)
-                    : ndl(l);
-  }
-  static constexpr int scr_x() {
-    int s = 0;
-    for (int l = 0; l < L; ++l) s = cmax(s, level_x(l));
-    return s;
-  }
-  static constexpr int scr_y() {
-    int s = 0;
-    for (int l = 0; l < L; ++l) s = cmax(s, level_y(l));
-    return s;
-  }
-  static constexpr int off_X = 3 * nd + lower_size(L - 2);
-  static constexpr int off_Y = off_X + scr_x();
-  static constexpr int size = cmax(phaseR_end, off_Y + scr_y());
-  static constexpr int off_res = DIM == 3 ? off_X : off_Y;
-  static constexpr int off_t1 = DIM == 3 ? off_Y : off_X;
+  static constexpr int off_X = 2 * nd + NRED + lower_size(L - 2);
+  static constexpr int phaseS_end = off_X + 2 * nd;
+  static constexpr int size1 = cmax(phaseR_end, phaseS_end);
+  static constexpr int off_cc = size1;
+  static constexpr int size = size1 + nd;
+  static_assert(NT <= 64 * NRED, "block_sum scratch");
 
-  // res = r - c A_l d on p-level l (interior patch operator)
+  // res = r - c A_l d on p-level l (interior patch operator); A, B scratch in X, res may
+  // be X itself (the last stage lands on A in place) or r
   template <int l>
   PMG_INLINE static void vmult_residual(int tid, T *lds, const DevTabs<T> &tb, T c, const T *d, const T *r,
                                         T *res) {
-    laplace_sf<DIM, PatInterior<qd(l)>, NT>(tid, d, res, r, c, tb.Kp[l], tb.Mp[l], lds + off_X, lds + off_Y);
+    constexpr int m = nl(l);
+    using Pat = PatInterior<qd(l)>;
+    using D = Dense<m, m>;
+    T *A = lds + off_X, *B = lds + off_X + ndl(l);
+    if constexpr (DIM == 3) {
+      scontract2<0, m, m, m, Pat, NT, D, D, D>(tid, d, A, tb.Mp[l], B, tb.Kp[l]);  // A = Mx d, B = Kx d
+      PMG_SYNC();
+      scontract_pair<1, m, m, m, Pat, NT, D, D>(tid, A, B, tb.Mp[l], tb.Kp[l]);  // C = My A, G = Ky A + My B
+      PMG_SYNC();
+      scontract_final<2, m, m, m, Pat, NT, D, D, D>(tid, A, B, res, r, c, tb.Kp[l], tb.Mp[l]);
+    } else {
+      scontract2<0, m, m, 1, Pat, NT, D, D, D>(tid, d, A, tb.Mp[l], B, tb.Kp[l]);
+      PMG_SYNC();
+      scontract_final<1, m, m, 1, Pat, NT, D, D, D>(tid, A, B, res, r, c, tb.Kp[l], tb.Mp[l]);
+    }
+  }
+
+  PMG_INLINE static void decode_l(int e, int m, int k[3]) {
+    k[0] = e % m;
+    k[1] = (e / m) % m;
+    k[2] = DIM == 3 ? e / (m * m) : 0;
   }
 
   // Alg. 3 on p-level l: d = V(l, r), zero initial guess.
@@ -128,21 +128,66 @@ struct PatchBody {
       if (tid == 0) d[0] = cinv * as_const(tb.invD[0])[0] * r[0];  // exact 1x1 solve
       PMG_SYNC();
     } else {
-      constexpr int q = qd(l), qc = qd(l - 1), ndq = ndl(l);
-      constexpr int t1size = DIM == 3 ? cmax(kron_t1(DIM, nl(l), nl(l - 1)), kron_t1(DIM, nl(l - 1), nl(l))) : 0;
+      constexpr int q = qd(l), qc = qd(l - 1), m = nl(l), mc = nl(l - 1), ndq = ndl(l);
       const cptr<T> invD = as_const(tb.invD[l]);
       for (int e = tid; e < ndq; e += NT) d[e] = cinv * invD[e] * r[e];  // pre-smoothing
       PMG_SYNC();
-      T *res = lds + off_res;
+      T *res = lds + off_X;
       vmult_residual<l>(tid, lds, tb, c, d, r, res);  // res = r - A d
       PMG_SYNC();
-      T *rc = lds + off_lr(l - 1), *dc = lds + off_ld(l - 1);
-      T *t1 = lds + off_t1, *t2 = t1 + t1size;
-      kron_all<DIM, PatRestrict<q, qc>, NT, false>(tid, res, rc, tb.TpT[l], t1, t2);
-      PMG_SYNC();
-      cycle<l - 1>(tid, lds, tb, c, cinv, rc, dc, full);
-      kron_all<DIM, PatProlong<q, qc>, NT, true>(tid, dc, d, tb.Tp[l], t1, t2);  // d += P e
-      PMG_SYNC();
+      if constexpr (l == 1) {
+        // the coarsest p-level has one node: restriction is a weighted sum, its exact
+        // solve a scalar, and prolongation the outer product of the embedding column
+        const cptr<T> w = as_const(tb.TpT[l]), t = as_const(tb.Tp[l]);
+        T part = 0;
+        for (int e = tid; e < ndq; e += NT) {
+          int k[3];
+          decode_l(e, m, k);
+          const T wk = DIM == 3 ? w[k[2]] : T(1);
+          part += w[k[0]] * w[k[1]] * wk * res[e];
+        }
+        const T r0 = block_sum<NT>(tid, part, lds + off_red);
+        const T d0 = cinv * as_const(tb.invD[0])[0] * r0;
+        for (int e = tid; e < ndq; e += NT) {
+          int k[3];
+          decode_l(e, m, k);
+          const T tk = DIM == 3 ? t[k[2]] : T(1);
+          d[e] += t[k[0]] * t[k[1]] * tk * d0;
+        }
+        PMG_SYNC();
+      } else {
+        using PR = PatRestrict<q, qc>;
+        using PP = PatProlong<q, qc>;
+        using D = Dense<m, m>;
+        using DC = Dense<mc, mc>;
+        T *rc = lds + off_lr(l - 1), *dc = lds + off_ld(l - 1);
+        T *X0 = lds + off_X, *X1 = lds + off_X + nd;
+        if constexpr (DIM == 3) {
+          scontract1<0, m, m, m, PR, NT, false, D, D>(tid, res, res, tb.TpT[l]);
+          PMG_SYNC();
+          scontract1<1, mc, m, m, PR, NT, false, D, D>(tid, res, res, tb.TpT[l]);
+          PMG_SYNC();
+          scontract1<2, mc, mc, m, PR, NT, false, D, DC>(tid, res, rc, tb.TpT[l]);
+        } else {
+          scontract1<0, m, m, 1, PR, NT, false, D, D>(tid, res, res, tb.TpT[l]);
+          PMG_SYNC();
+          scontract1<1, mc, m, 1, PR, NT, false, D, DC>(tid, res, rc, tb.TpT[l]);
+        }
+        PMG_SYNC();
+        cycle<l - 1>(tid, lds, tb, c, cinv, rc, dc, full);
+        if constexpr (DIM == 3) {  // d += P dc
+          scontract1<0, mc, mc, mc, PP, NT, false, DC, Dense<m, mc>>(tid, dc, X0, tb.Tp[l]);
+          PMG_SYNC();
+          scontract1<1, m, mc, mc, PP, NT, false, Dense<m, mc>, D>(tid, X0, X1, tb.Tp[l]);
+          PMG_SYNC();
+          scontract1<2, m, m, mc, PP, NT, true, D, D>(tid, X1, d, tb.Tp[l]);
+        } else {
+          scontract1<0, mc, mc, 1, PP, NT, false, DC, Dense<m, mc>>(tid, dc, X0, tb.Tp[l]);
+          PMG_SYNC();
+          scontract1<1, m, mc, 1, PP, NT, true, Dense<m, mc>, D>(tid, X0, d, tb.Tp[l]);
+        }
+        PMG_SYNC();
+      }
       if (full) {  // post-smoothing
         vmult_residual<l>(tid, lds, tb, c, d, r, res);
         PMG_SYNC();
@@ -166,6 +211,9 @@ struct PatchBody {
       PMG_SYNC();
     }
   }
+
+  // Arena elements for n_iter Richardson steps.
+  PMG_HD static constexpr int arena(int n_iter) { return n_iter > 1 ? size : size1; }
 
   PMG_INLINE static void decode(int idx, int k[3]) {
     k[0] = idx % n;
@@ -198,7 +246,23 @@ struct PatchBody {
     }
     PMG_SYNC();
     // r = b - c (sum_k Kr_k (x) Mr_others) ubar   (closure -> interior)
-    laplace_sf<DIM, PatResidual<P>, NT>(tid, ucl, r, r, a.c, a.tb.Kr, a.tb.Mr, lds + off_abR, ucl);
+    {
+      using Pat = PatResidual<P>;
+      using DU = Dense<N, N>;
+      using DB = Dense<n, N>;
+      T *Bb = lds + off_B;
+      if constexpr (DIM == 3) {
+        scontract2<0, N, N, N, Pat, NT, DU, DU, DB>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
+        PMG_SYNC();
+        scontract_pair<1, n, N, N, Pat, NT, DU, DB>(tid, ucl, Bb, a.tb.Mr, a.tb.Kr);
+        PMG_SYNC();
+        scontract_final<2, n, n, N, Pat, NT, DU, DB, Dense<n, n>>(tid, ucl, Bb, r, r, a.c, a.tb.Kr, a.tb.Mr);
+      } else {
+        scontract2<0, N, N, 1, Pat, NT, DU, DU, DB>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
+        PMG_SYNC();
+        scontract_final<1, n, N, 1, Pat, NT, DU, DB, Dense<n, n>>(tid, ucl, Bb, r, r, a.c, a.tb.Kr, a.tb.Mr);
+      }
+    }
     PMG_SYNC();
     local_solve(tid, lds, a);
     const T *d = lds + off_d;

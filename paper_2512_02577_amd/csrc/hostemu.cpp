@@ -55,7 +55,7 @@ struct EmuSmooth {
   struct F {
     static int run(const SmoothArgs<double> &base, int n, int color_dir, bool local_only, int n_blocks) {
       using B = PatchBody<DIM, double, 1, P, H>;
-      std::vector<double> lds(B::size);
+      std::vector<double> lds(B::arena(base.n_iter));  // exactly what the device launch gets
       if (local_only) {
         for (int blk = 0; blk < n_blocks; ++blk) B::local_only(0, blk, lds.data(), base);
         return 0;

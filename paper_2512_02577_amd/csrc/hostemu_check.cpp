@@ -43,12 +43,17 @@ int main() {
           if (dim == 3 && p >= 7 && n > 3) continue;
           const long N = ipow((long)p * n + 1, dim);
           auto u = rnd(N, 1), b = rnd(N, 2), out = std::vector<double>(N);
-          for (int full = 0; full < 2; ++full)
-            fails += pmgemu_smooth(dim, n, p, deg.data(), (int)deg.size(), om.data(), full, 2, 1, u.data(), b.data()) != 0;
+          // one Richardson step uses the smaller arena: check both sizes
+          for (int it = 1; it <= 2; ++it)
+            for (int full = 0; full < 2; ++full)
+              fails += pmgemu_smooth(dim, n, p, deg.data(), (int)deg.size(), om.data(), full, it, 1, u.data(),
+                                     b.data()) != 0;
           const long nd = ipow(2 * p - 1, dim), np = ipow(n - 1, dim);
           auto r = rnd(nd * np, 3);
           std::vector<double> d(nd * np);
-          fails += pmgemu_local_solve(dim, n, p, deg.data(), (int)deg.size(), om.data(), 0, 2, (int)np, r.data(), d.data()) != 0;
+          for (int it = 1; it <= 2; ++it)
+            fails += pmgemu_local_solve(dim, n, p, deg.data(), (int)deg.size(), om.data(), 0, it, (int)np, r.data(),
+                                        d.data()) != 0;
           if (code == 0) {
             fails += pmgemu_apply(dim, n, p, 1, u.data(), b.data(), out.data()) != 0;
             const long Nc = ipow((long)p * n + 1, dim), Nf = ipow(2L * p * n + 1, dim);

@@ -94,10 +94,10 @@ int launch_arena(KL klds, KG kglob, int nblk, int threads, size_t bytes, const A
     const int grid = nblk < ar.slots ? nblk : ar.slots;
     hipLaunchKernelGGL(kglob, dim3(grid), dim3(threads), 0, s, args..., ar.global);
   } else {
-    if (bytes > 65536) {
+    if (bytes > 65536) {  // raise the kernel's limit once, to the device maximum
       static thread_local const void *last = nullptr;
       if (last != (const void *)klds) {
-        if (hipFuncSetAttribute((const void *)klds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+        if (hipFuncSetAttribute((const void *)klds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ar.lds_max) !=
             hipSuccess)
           return -4;
         last = (const void *)klds;
@@ -117,7 +117,7 @@ struct SmoothL {
       static int run(const SmoothArgs<T> &a, const Arena &ar, hipStream_t s) {
         using B = PatchBody<DIM, T, patch_threads(P), P, H>;
         return launch_arena(k_smooth<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, patch_threads(P),
-                            B::size * sizeof(T), ar, s, a);
+                            B::arena(a.n_iter) * sizeof(T), ar, s, a);
       }
     };
   };
@@ -132,7 +132,7 @@ struct LocalL {
       static int run(const SmoothArgs<T> &a, int nb, const Arena &ar, hipStream_t s) {
         using B = PatchBody<DIM, T, patch_threads(P), P, H>;
         return launch_arena(k_local<DIM, T, P, H>, k_local_g<DIM, T, P, H>, nb, patch_threads(P),
-                            B::size * sizeof(T), ar, s, a, nb);
+                            B::arena(a.n_iter) * sizeof(T), ar, s, a, nb);
       }
     };
   };

@@ -269,4 +269,166 @@ PMG_INLINE void kron_all(int tid, const T *in, T *out, const T *Mat, T *t1, T *t
 constexpr int kron_t1(int dim, int I, int O) { return dim == 3 ? O * I * I : O * I; }
 constexpr int kron_t2(int dim, int I, int O) { return dim == 3 ? O * O * I : 0; }
 
+// ---- strided pencils (contractions that may run in place) --------------------------------
+// A tensor of logical extents (E0, E1, E2) stored with strides (1, S1, S2).  A contraction
+// along AX reads each pencil into registers and writes its NOUT <= NIN outputs to the
+// pencil positions 0..NOUT-1 of the output layout; since a pencil is read completely by
+// the lane that owns it before that lane writes, and pencils of one axis are disjoint,
+// the output may be the input buffer itself (same layout): no barrier between read and
+// write, and no separate stage buffer.
+template <int S1_, int S2_>
+struct Lay {
+  static constexpr int S1 = S1_, S2 = S2_;
+};
+template <int E0, int E1>
+using Dense = Lay<E0, E0 * E1>;  // compact layout of extents (E0, E1, *)
+
+template <int AX, int E0, int E1, int E2>
+struct Pen {
+  static constexpr int NIN = AX == 0 ? E0 : (AX == 1 ? E1 : E2);
+  static constexpr int NA = AX == 0 ? E1 : E0;  // extent of the first other axis
+  static constexpr int NB = AX == 2 ? E1 : E2;  // extent of the second other axis
+  static constexpr int NPEN = NA * NB;
+  template <class L>
+  PMG_INLINE static int base(int pen) {
+    const int a = pen % NA, b = pen / NA;
+    return AX == 0 ? a * L::S1 + b * L::S2 : (AX == 1 ? a + b * L::S2 : a + b * L::S1);
+  }
+  template <class L>
+  static constexpr int step() {
+    return AX == 0 ? 1 : (AX == 1 ? L::S1 : L::S2);
+  }
+};
+
+// oa = A in (layout LA), ob = B in (layout LB); oa may be in (LA = LI)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, class LI, class LA, class LB, typename T>
+PMG_INLINE void scontract2(int tid, const T *in, T *oa, const T *A_, T *ob, const T *B_) {
+  using X = Pen<AX, E0, E1, E2>;
+  const cptr<T> A = as_const(A_), B = as_const(B_);
+  static_assert(X::NIN == Pat::nin, "extent mismatch");
+  for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const int ib = X::template base<LI>(pen), oab = X::template base<LA>(pen), obb = X::template base<LB>(pen);
+    T v[Pat::nin];
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::template step<LI>()];
+#pragma unroll
+    for (int o = 0; o < Pat::nout; ++o) {
+      T sa = 0, sb = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) {
+          sa += A[o * Pat::nin + i] * v[i];
+          sb += B[o * Pat::nin + i] * v[i];
+        }
+      oa[oab + o * X::template step<LA>()] = sa;
+      ob[obb + o * X::template step<LB>()] = sb;
+    }
+  }
+}
+
+// ia <- M ia, ib <- K ia + M ib, in place (layouts LA, LB)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, class LA, class LB, typename T>
+PMG_INLINE void scontract_pair(int tid, T *ia, T *ib, const T *M_, const T *K_) {
+  using X = Pen<AX, E0, E1, E2>;
+  const cptr<T> M = as_const(M_), K = as_const(K_);
+  static_assert(X::NIN == Pat::nin, "extent mismatch");
+  for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen);
+    T va[Pat::nin], vb[Pat::nin];
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) {
+      va[i] = ia[ab + i * X::template step<LA>()];
+      vb[i] = ib[bb + i * X::template step<LB>()];
+    }
+#pragma unroll
+    for (int o = 0; o < Pat::nout; ++o) {
+      T sc = 0, sg = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) {
+          const T m = M[o * Pat::nin + i];
+          sc += m * va[i];
+          sg += K[o * Pat::nin + i] * va[i] + m * vb[i];
+        }
+      ia[ab + o * X::template step<LA>()] = sc;
+      ib[bb + o * X::template step<LB>()] = sg;
+    }
+  }
+}
+
+// out = base - s (K ia + M ib) (base may be out), out in layout LO; out may be ia (LO = LA)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, class LA, class LB, class LO, typename T>
+PMG_INLINE void scontract_final(int tid, const T *ia, const T *ib, T *out, const T *base, T s, const T *K_,
+                                const T *M_) {
+  using X = Pen<AX, E0, E1, E2>;
+  const cptr<T> K = as_const(K_), M = as_const(M_);
+  static_assert(X::NIN == Pat::nin, "extent mismatch");
+  for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen), ob = X::template base<LO>(pen);
+    T va[Pat::nin], vb[Pat::nin];
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) {
+      va[i] = ia[ab + i * X::template step<LA>()];
+      vb[i] = ib[bb + i * X::template step<LB>()];
+    }
+#pragma unroll
+    for (int o = 0; o < Pat::nout; ++o) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += K[o * Pat::nin + i] * va[i] + M[o * Pat::nin + i] * vb[i];
+      const int oi = ob + o * X::template step<LO>();
+      out[oi] = base[oi] - s * acc;
+    }
+  }
+}
+
+// out = Mat in (ADD: out += Mat in); out may be in (LO = LI, NOUT <= NIN)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, bool ADD, class LI, class LO, typename T>
+PMG_INLINE void scontract1(int tid, const T *in, T *out, const T *Mat_) {
+  using X = Pen<AX, E0, E1, E2>;
+  const cptr<T> Mat = as_const(Mat_);
+  static_assert(X::NIN == Pat::nin, "extent mismatch");
+  for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const int ib = X::template base<LI>(pen), ob = X::template base<LO>(pen);
+    T v[Pat::nin];
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::template step<LI>()];
+#pragma unroll
+    for (int o = 0; o < Pat::nout; ++o) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * v[i];
+      const int oi = ob + o * X::template step<LO>();
+      if (ADD)
+        out[oi] += acc;
+      else
+        out[oi] = acc;
+    }
+  }
+}
+
+// Sum over the workgroup of one value per lane; every lane gets the total.  red: NT/64
+// (at least 1) elements of LDS scratch.  On the host (NT = 1) the value itself.
+template <int NT, typename T>
+PMG_INLINE T block_sum(int tid, T v, T *red) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  constexpr int NW = NT / 64 > 0 ? NT / 64 : 1;
+  if (NW == 1) return v;
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  T s = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += red[w];
+  __syncthreads();
+  return s;
+#else
+  (void)tid;
+  (void)red;
+  return v;
+#endif
+}
+
 }  // namespace pmg

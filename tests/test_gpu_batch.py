@@ -159,13 +159,18 @@ def test_batch_stats_and_rejections():
     one = pmg.batch_create([make(4, 3), make(6, 3)])
     s1, l1 = pmg.batch_stats(one, pmg.FP64)
     assert s1 == l1
-    p8 = pmg.batch_create([make(2, 8)])
-    with pytest.raises(pmg.PmgError) as e:
-        pmg.batch_stats(p8, pmg.FP64)
-    assert e.value.status == pmg.ERR_UNSUPPORTED
+    # FP64 p=8: the patch arena of one Richardson step fits the LDS, that of two does not
     b8 = dev(rhs_vector(3, 2, 8, 3))
     x8 = torch.empty_like(b8)
-    assert pmg.batch_solve(p8, [b8], [x8], pmg.FP32)[0].rel_residual <= 1e-8
+    p8 = pmg.batch_create([make(2, 8)])
+    assert pmg.batch_solve(p8, [b8], [x8], pmg.FP64)[0].rel_residual <= 1e-8
+    cfg = pmg.default_config()
+    cfg.n_local_iter = 2
+    p8two = pmg.batch_create([pmg.make_problem(3, 2, 8, config=cfg)])
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.batch_stats(p8two, pmg.FP64)
+    assert e.value.status == pmg.ERR_UNSUPPORTED
+    assert pmg.batch_solve(p8two, [b8], [x8], pmg.FP32)[0].rel_residual <= 1e-8
     for bad, code in (([pmg.make_problem(2, 8, 3)], pmg.ERR_UNSUPPORTED),
                       ([pmg.make_problem(3, 4, 3, vertices=jittered_vertices(3, 4, 0.1, 1))], pmg.ERR_UNSUPPORTED),
                       ([pmg.make_problem(3, 4, 3, p_levels=[1, 2, 3])], pmg.ERR_UNSUPPORTED),
