@@ -106,11 +106,11 @@ struct PatchBody {
       PMG_SYNC();
       scontract_pair<1, m, m, m, Pat, NT, D, D>(tid, A, B, tb.Mp[l], tb.Kp[l]);  // C = My A, G = Ky A + My B
       PMG_SYNC();
-      scontract_final<2, m, m, m, Pat, NT, D, D, D>(tid, A, B, res, r, c, tb.Kp[l], tb.Mp[l]);
+      scontract_final<2, m, m, m, Pat, NT, D, D, D, true>(tid, A, B, res, r, c, tb.Kp[l], tb.Mp[l]);
     } else {
       scontract2<0, m, m, 1, Pat, NT, D, D, D>(tid, d, A, tb.Mp[l], B, tb.Kp[l]);
       PMG_SYNC();
-      scontract_final<1, m, m, 1, Pat, NT, D, D, D>(tid, A, B, res, r, c, tb.Kp[l], tb.Mp[l]);
+      scontract_final<1, m, m, 1, Pat, NT, D, D, D, true>(tid, A, B, res, r, c, tb.Kp[l], tb.Mp[l]);
     }
   }
 
@@ -163,13 +163,13 @@ struct PatchBody {
         T *rc = lds + off_lr(l - 1), *dc = lds + off_ld(l - 1);
         T *X0 = lds + off_X, *X1 = lds + off_X + nd;
         if constexpr (DIM == 3) {
-          scontract1<0, m, m, m, PR, NT, false, D, D>(tid, res, res, tb.TpT[l]);
+          scontract1<0, m, m, m, PR, NT, false, D, D, true>(tid, res, res, tb.TpT[l]);
           PMG_SYNC();
-          scontract1<1, mc, m, m, PR, NT, false, D, D>(tid, res, res, tb.TpT[l]);
+          scontract1<1, mc, m, m, PR, NT, false, D, D, true>(tid, res, res, tb.TpT[l]);
           PMG_SYNC();
           scontract1<2, mc, mc, m, PR, NT, false, D, DC>(tid, res, rc, tb.TpT[l]);
         } else {
-          scontract1<0, m, m, 1, PR, NT, false, D, D>(tid, res, res, tb.TpT[l]);
+          scontract1<0, m, m, 1, PR, NT, false, D, D, true>(tid, res, res, tb.TpT[l]);
           PMG_SYNC();
           scontract1<1, mc, m, 1, PR, NT, false, D, DC>(tid, res, rc, tb.TpT[l]);
         }
@@ -232,6 +232,19 @@ struct PatchBody {
     const int g0[3] = {P * (v[0] - 1), P * (v[1] - 1), DIM == 3 ? P * (v[2] - 1) : 0};
     T *ucl = lds + off_ucl, *r = lds + off_r;
     const T *__restrict__ u_in = a.u;
+    // The patch interior of u is written only by this patch while its color runs (no
+    // other patch of the color has it in its closure), so the values the final update
+    // adds to can be read now, with the gathers, instead of after the local solve.
+    constexpr int NUI = (nd + NT - 1) / NT;
+    constexpr bool KEEP = NUI <= 2;
+    T uold[KEEP ? NUI : 1];
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int k = 0; k < NUI; ++k) {
+        const int e = tid + k * NT;
+        if (e < nd) uold[k] = u_in[interior_index(e, g0, m)];
+      }
+    }
     for (int e = tid; e < Nd; e += NT) {
       const int i = e % N, j = (e / N) % N, k = DIM == 3 ? e / (N * N) : 0;
       const int gx = g0[0] + i, gy = g0[1] + j, gz = g0[2] + k;
@@ -239,11 +252,7 @@ struct PatchBody {
       if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
       ucl[e] = bnd ? T(0) : u_in[gx + m * (gy + m * gz)];
     }
-    for (int e = tid; e < nd; e += NT) {
-      int k[3];
-      decode(e, k);
-      r[e] = a.b[(g0[0] + 1 + k[0]) + m * ((g0[1] + 1 + k[1]) + m * (g0[2] + (DIM == 3 ? 1 : 0) + k[2]))];
-    }
+    for (int e = tid; e < nd; e += NT) r[e] = a.b[interior_index(e, g0, m)];
     PMG_SYNC();
     // r = b - c (sum_k Kr_k (x) Mr_others) ubar   (closure -> interior)
     {
@@ -252,13 +261,13 @@ struct PatchBody {
       using DB = Dense<n, N>;
       T *Bb = lds + off_B;
       if constexpr (DIM == 3) {
-        scontract2<0, N, N, N, Pat, NT, DU, DU, DB>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
+        scontract2<0, N, N, N, Pat, NT, DU, DU, DB, true>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
         PMG_SYNC();
         scontract_pair<1, n, N, N, Pat, NT, DU, DB>(tid, ucl, Bb, a.tb.Mr, a.tb.Kr);
         PMG_SYNC();
         scontract_final<2, n, n, N, Pat, NT, DU, DB, Dense<n, n>>(tid, ucl, Bb, r, r, a.c, a.tb.Kr, a.tb.Mr);
       } else {
-        scontract2<0, N, N, 1, Pat, NT, DU, DU, DB>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
+        scontract2<0, N, N, 1, Pat, NT, DU, DU, DB, true>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
         PMG_SYNC();
         scontract_final<1, n, N, 1, Pat, NT, DU, DB, Dense<n, n>>(tid, ucl, Bb, r, r, a.c, a.tb.Kr, a.tb.Mr);
       }
@@ -266,12 +275,22 @@ struct PatchBody {
     PMG_SYNC();
     local_solve(tid, lds, a);
     const T *d = lds + off_d;
-    for (int e = tid; e < nd; e += NT) {
-      int k[3];
-      decode(e, k);
-      const int gi = (g0[0] + 1 + k[0]) + m * ((g0[1] + 1 + k[1]) + m * (g0[2] + (DIM == 3 ? 1 : 0) + k[2]));
-      a.u[gi] += d[e];
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int k = 0; k < NUI; ++k) {
+        const int e = tid + k * NT;
+        if (e < nd) a.u[interior_index(e, g0, m)] = uold[k] + d[e];
+      }
+    } else {
+      for (int e = tid; e < nd; e += NT) a.u[interior_index(e, g0, m)] += d[e];
     }
+  }
+
+  // global index of patch-interior element e of the patch whose closure starts at g0
+  PMG_INLINE static int interior_index(int e, const int g0[3], int m) {
+    int k[3];
+    decode(e, k);
+    return (g0[0] + 1 + k[0]) + m * ((g0[1] + 1 + k[1]) + m * (g0[2] + (DIM == 3 ? 1 : 0) + k[2]));
   }
 
   // LocalSolve alone on block blk of r_blocks -> d_blocks

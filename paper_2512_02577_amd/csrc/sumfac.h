@@ -300,106 +300,177 @@ struct Pen {
   }
 };
 
-// oa = A in (layout LA), ob = B in (layout LB); oa may be in (LA = LI)
-template <int AX, int E0, int E1, int E2, class Pat, int NT, class LI, class LA, class LB, typename T>
-PMG_INLINE void scontract2(int tid, const T *in, T *oa, const T *A_, T *ob, const T *B_) {
+// Work split of one contraction stage.  When the workgroup has more waves than the
+// stage has pencils to fill, the waves are grouped into `parts` (PW waves each, enough for
+// all pencils) and part k computes the outputs [lo(k), hi(k)) of every pencil: each wave
+// reads whole pencils but does a share of the multiply-adds, which shortens the stage
+// (the latency of a patch is a chain of such stages).  The part is wave-uniform, so the
+// output range is a compile-time constant in every branch and the matrix entries stay
+// scalar operands.  A split stage that writes in place (INPL) has a barrier between
+// reading the pencils and writing them, since another part may still read what one part
+// overwrites.  On the host (NT = 1) there is one part.
+template <int NPEN, int NOUT, int NT>
+struct WSplit {
+  static constexpr int NW = NT / 64;
+  static constexpr int PW = (NPEN + 63) / 64;
+  static constexpr int P0 = NW >= 2 * PW ? NW / PW : 1;
+  static constexpr int parts = P0 < NOUT ? P0 : NOUT;
+  static constexpr int lo(int k) { return k * NOUT / parts; }
+  static constexpr int hi(int k) { return (k + 1) * NOUT / parts; }
+  // f.load(pen, regs); f.template store<lo(k), hi(k)>(pen, regs) for this lane's pencils
+  template <bool INPL, class F>
+  PMG_INLINE static void each(int tid, const F &f) {
+    typename F::Regs r;
+    if constexpr (parts == 1) {
+      for (int pen = tid; pen < NPEN; pen += NT) {
+        f.load(pen, r);
+        f.template store<0, NOUT>(pen, r);
+      }
+    } else {
+      const int part = tid / (64 * PW), pen = tid % (64 * PW);
+      const bool act = part < parts && pen < NPEN;
+      if (act) f.load(pen, r);
+      if constexpr (INPL) PMG_SYNC();
+      if (act) dispatch<0>(part, pen, r, f);
+    }
+  }
+  template <int K, class F>
+  PMG_INLINE static void dispatch(int part, int pen, const typename F::Regs &r, const F &f) {
+    if constexpr (K < parts) {
+      if (part == K)
+        f.template store<lo(K), hi(K)>(pen, r);
+      else
+        dispatch<K + 1>(part, pen, r, f);
+    }
+  }
+};
+
+// Pencil functors of the contractions below: load a pencil into registers, then produce
+// the outputs [O0, O1) of it.
+template <int AX, int E0, int E1, int E2, class Pat, class LI, class LA, class LB, typename T>
+struct FC2 {  // oa = A in, ob = B in
   using X = Pen<AX, E0, E1, E2>;
-  const cptr<T> A = as_const(A_), B = as_const(B_);
-  static_assert(X::NIN == Pat::nin, "extent mismatch");
-  for (int pen = tid; pen < X::NPEN; pen += NT) {
-    const int ib = X::template base<LI>(pen), oab = X::template base<LA>(pen), obb = X::template base<LB>(pen);
+  const T *in;
+  T *oa, *ob;
+  cptr<T> A, B;
+  struct Regs {
     T v[Pat::nin];
+  };
+  PMG_INLINE void load(int pen, Regs &r) const {
+    const int ib = X::template base<LI>(pen);
 #pragma unroll
-    for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::template step<LI>()];
+    for (int i = 0; i < Pat::nin; ++i) r.v[i] = in[ib + i * X::template step<LI>()];
+  }
+  template <int O0, int O1>
+  PMG_INLINE void store(int pen, const Regs &r) const {
+    const int oab = X::template base<LA>(pen), obb = X::template base<LB>(pen);
 #pragma unroll
-    for (int o = 0; o < Pat::nout; ++o) {
+    for (int o = O0; o < O1; ++o) {
       T sa = 0, sb = 0;
 #pragma unroll
       for (int i = 0; i < Pat::nin; ++i)
         if (i >= Pat::lo(o) && i < Pat::hi(o)) {
-          sa += A[o * Pat::nin + i] * v[i];
-          sb += B[o * Pat::nin + i] * v[i];
+          sa += A[o * Pat::nin + i] * r.v[i];
+          sb += B[o * Pat::nin + i] * r.v[i];
         }
       oa[oab + o * X::template step<LA>()] = sa;
       ob[obb + o * X::template step<LB>()] = sb;
     }
   }
-}
+};
 
-// ia <- M ia, ib <- K ia + M ib, in place (layouts LA, LB)
-template <int AX, int E0, int E1, int E2, class Pat, int NT, class LA, class LB, typename T>
-PMG_INLINE void scontract_pair(int tid, T *ia, T *ib, const T *M_, const T *K_) {
+template <int AX, int E0, int E1, int E2, class Pat, class LA, class LB, typename T>
+struct FCPair {  // ia <- M ia, ib <- K ia + M ib
   using X = Pen<AX, E0, E1, E2>;
-  const cptr<T> M = as_const(M_), K = as_const(K_);
-  static_assert(X::NIN == Pat::nin, "extent mismatch");
-  for (int pen = tid; pen < X::NPEN; pen += NT) {
-    const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen);
+  T *ia, *ib;
+  cptr<T> M, K;
+  struct Regs {
     T va[Pat::nin], vb[Pat::nin];
+  };
+  PMG_INLINE void load(int pen, Regs &r) const {
+    const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen);
 #pragma unroll
     for (int i = 0; i < Pat::nin; ++i) {
-      va[i] = ia[ab + i * X::template step<LA>()];
-      vb[i] = ib[bb + i * X::template step<LB>()];
+      r.va[i] = ia[ab + i * X::template step<LA>()];
+      r.vb[i] = ib[bb + i * X::template step<LB>()];
     }
+  }
+  template <int O0, int O1>
+  PMG_INLINE void store(int pen, const Regs &r) const {
+    const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen);
 #pragma unroll
-    for (int o = 0; o < Pat::nout; ++o) {
+    for (int o = O0; o < O1; ++o) {
       T sc = 0, sg = 0;
 #pragma unroll
       for (int i = 0; i < Pat::nin; ++i)
         if (i >= Pat::lo(o) && i < Pat::hi(o)) {
           const T m = M[o * Pat::nin + i];
-          sc += m * va[i];
-          sg += K[o * Pat::nin + i] * va[i] + m * vb[i];
+          sc += m * r.va[i];
+          sg += K[o * Pat::nin + i] * r.va[i] + m * r.vb[i];
         }
       ia[ab + o * X::template step<LA>()] = sc;
       ib[bb + o * X::template step<LB>()] = sg;
     }
   }
-}
+};
 
-// out = base - s (K ia + M ib) (base may be out), out in layout LO; out may be ia (LO = LA)
-template <int AX, int E0, int E1, int E2, class Pat, int NT, class LA, class LB, class LO, typename T>
-PMG_INLINE void scontract_final(int tid, const T *ia, const T *ib, T *out, const T *base, T s, const T *K_,
-                                const T *M_) {
+template <int AX, int E0, int E1, int E2, class Pat, class LA, class LB, class LO, typename T>
+struct FCFinal {  // out = base - s (K ia + M ib)
   using X = Pen<AX, E0, E1, E2>;
-  const cptr<T> K = as_const(K_), M = as_const(M_);
-  static_assert(X::NIN == Pat::nin, "extent mismatch");
-  for (int pen = tid; pen < X::NPEN; pen += NT) {
-    const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen), ob = X::template base<LO>(pen);
+  const T *ia, *ib;
+  T *out;
+  const T *base;
+  T s;
+  cptr<T> K, M;
+  struct Regs {
     T va[Pat::nin], vb[Pat::nin];
+  };
+  PMG_INLINE void load(int pen, Regs &r) const {
+    const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen);
 #pragma unroll
     for (int i = 0; i < Pat::nin; ++i) {
-      va[i] = ia[ab + i * X::template step<LA>()];
-      vb[i] = ib[bb + i * X::template step<LB>()];
+      r.va[i] = ia[ab + i * X::template step<LA>()];
+      r.vb[i] = ib[bb + i * X::template step<LB>()];
     }
+  }
+  template <int O0, int O1>
+  PMG_INLINE void store(int pen, const Regs &r) const {
+    const int ob = X::template base<LO>(pen);
 #pragma unroll
-    for (int o = 0; o < Pat::nout; ++o) {
+    for (int o = O0; o < O1; ++o) {
       T acc = 0;
 #pragma unroll
       for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += K[o * Pat::nin + i] * va[i] + M[o * Pat::nin + i] * vb[i];
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += K[o * Pat::nin + i] * r.va[i] + M[o * Pat::nin + i] * r.vb[i];
       const int oi = ob + o * X::template step<LO>();
       out[oi] = base[oi] - s * acc;
     }
   }
-}
+};
 
-// out = Mat in (ADD: out += Mat in); out may be in (LO = LI, NOUT <= NIN)
-template <int AX, int E0, int E1, int E2, class Pat, int NT, bool ADD, class LI, class LO, typename T>
-PMG_INLINE void scontract1(int tid, const T *in, T *out, const T *Mat_) {
+template <int AX, int E0, int E1, int E2, class Pat, bool ADD, class LI, class LO, typename T>
+struct FC1 {  // out (=|+=) Mat in
   using X = Pen<AX, E0, E1, E2>;
-  const cptr<T> Mat = as_const(Mat_);
-  static_assert(X::NIN == Pat::nin, "extent mismatch");
-  for (int pen = tid; pen < X::NPEN; pen += NT) {
-    const int ib = X::template base<LI>(pen), ob = X::template base<LO>(pen);
+  const T *in;
+  T *out;
+  cptr<T> Mat;
+  struct Regs {
     T v[Pat::nin];
+  };
+  PMG_INLINE void load(int pen, Regs &r) const {
+    const int ib = X::template base<LI>(pen);
 #pragma unroll
-    for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::template step<LI>()];
+    for (int i = 0; i < Pat::nin; ++i) r.v[i] = in[ib + i * X::template step<LI>()];
+  }
+  template <int O0, int O1>
+  PMG_INLINE void store(int pen, const Regs &r) const {
+    const int ob = X::template base<LO>(pen);
 #pragma unroll
-    for (int o = 0; o < Pat::nout; ++o) {
+    for (int o = O0; o < O1; ++o) {
       T acc = 0;
 #pragma unroll
       for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * v[i];
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * r.v[i];
       const int oi = ob + o * X::template step<LO>();
       if (ADD)
         out[oi] += acc;
@@ -407,6 +478,42 @@ PMG_INLINE void scontract1(int tid, const T *in, T *out, const T *Mat_) {
         out[oi] = acc;
     }
   }
+};
+
+// oa = A in (layout LA), ob = B in (layout LB); INPL: oa is in (LA = LI)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, class LI, class LA, class LB, bool INPL = false,
+          typename T>
+PMG_INLINE void scontract2(int tid, const T *in, T *oa, const T *A_, T *ob, const T *B_) {
+  using F = FC2<AX, E0, E1, E2, Pat, LI, LA, LB, T>;
+  static_assert(F::X::NIN == Pat::nin, "extent mismatch");
+  WSplit<F::X::NPEN, Pat::nout, NT>::template each<INPL>(tid, F{in, oa, ob, as_const(A_), as_const(B_)});
+}
+
+// ia <- M ia, ib <- K ia + M ib, in place (layouts LA, LB)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, class LA, class LB, typename T>
+PMG_INLINE void scontract_pair(int tid, T *ia, T *ib, const T *M_, const T *K_) {
+  using F = FCPair<AX, E0, E1, E2, Pat, LA, LB, T>;
+  static_assert(F::X::NIN == Pat::nin, "extent mismatch");
+  WSplit<F::X::NPEN, Pat::nout, NT>::template each<true>(tid, F{ia, ib, as_const(M_), as_const(K_)});
+}
+
+// out = base - s (K ia + M ib) (base may be out), out in layout LO; INPL: out is ia
+template <int AX, int E0, int E1, int E2, class Pat, int NT, class LA, class LB, class LO, bool INPL = false,
+          typename T>
+PMG_INLINE void scontract_final(int tid, const T *ia, const T *ib, T *out, const T *base, T s, const T *K_,
+                                const T *M_) {
+  using F = FCFinal<AX, E0, E1, E2, Pat, LA, LB, LO, T>;
+  static_assert(F::X::NIN == Pat::nin, "extent mismatch");
+  WSplit<F::X::NPEN, Pat::nout, NT>::template each<INPL>(tid, F{ia, ib, out, base, s, as_const(K_), as_const(M_)});
+}
+
+// out = Mat in (ADD: out += Mat in); INPL: out is in (LO = LI, NOUT <= NIN)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, bool ADD, class LI, class LO, bool INPL = false,
+          typename T>
+PMG_INLINE void scontract1(int tid, const T *in, T *out, const T *Mat_) {
+  using F = FC1<AX, E0, E1, E2, Pat, ADD, LI, LO, T>;
+  static_assert(F::X::NIN == Pat::nin, "extent mismatch");
+  WSplit<F::X::NPEN, Pat::nout, NT>::template each<INPL>(tid, F{in, out, as_const(Mat_)});
 }
 
 // Sum over the workgroup of one value per lane; every lane gets the total.  red: NT/64
