@@ -762,6 +762,7 @@ int pmg_device_init(pmg_problem *pr) {
   PMG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pr->device));
   PMG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pr->device));
   pr->arena.lds_max = (size_t)lds;
+  pr->arena.ncu = ncu > 0 ? ncu : 256;
   int rc = PMG_OK;
   auto bail = [&](int code) {
     release(pr);

@@ -28,6 +28,15 @@ __global__ __launch_bounds__(patch_threads(P), smooth_waves(DIM, sizeof(T), P)) 
   B::smooth_patch(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
+// Latency variant for small launches (few patches per CU, as on coarse h-levels): 256
+// lanes per patch, so that the short contraction stages split their outputs over four
+// waves and each patch finishes sooner.
+template <int DIM, typename T, int P, class H>
+__global__ __launch_bounds__(256) void k_smooth_w(SmoothArgs<T> a) {
+  using B = PatchBody<DIM, T, 256, P, H>;
+  B::smooth_patch(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+}
+
 template <int DIM, typename T, int P, class H>
 __global__ __launch_bounds__(patch_threads(P)) void k_smooth_g(SmoothArgs<T> a, void *garena) {
   using B = PatchBody<DIM, T, patch_threads(P), P, H>;
@@ -116,8 +125,12 @@ struct SmoothL {
     struct F {
       static int run(const SmoothArgs<T> &a, const Arena &ar, hipStream_t s) {
         using B = PatchBody<DIM, T, patch_threads(P), P, H>;
-        return launch_arena(k_smooth<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, patch_threads(P),
-                            B::arena(a.n_iter) * sizeof(T), ar, s, a);
+        const size_t bytes = B::arena(a.n_iter) * sizeof(T);
+        if constexpr (patch_threads(P) < 256)
+          if (a.n_patch <= kWideLaunch * ar.ncu && bytes <= ar.lds_max)
+            return launch_arena(k_smooth_w<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256, bytes, ar, s, a);
+        return launch_arena(k_smooth<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, patch_threads(P), bytes, ar,
+                            s, a);
       }
     };
   };

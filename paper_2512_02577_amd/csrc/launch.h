@@ -14,7 +14,11 @@ struct Arena {
   void *global = nullptr;  // device buffer, or nullptr when every kernel fits in LDS
   int slots = 0;           // workgroups the global buffer has room for
   size_t lds_max = 0;      // bytes of LDS a workgroup may use on this device
+  int ncu = 256;           // compute units of the device
 };
+
+// Patch launches with at most this many patches per CU use the 256-lane latency variant.
+constexpr int kWideLaunch = 4;
 
 // Kernel launchers of one (dimension, precision); instantiated in kernels_<d>d_<prec>.hip.
 template <int DIM, typename T>
