@@ -12,7 +12,7 @@ whole path).  value = nodes x V-cycles / time (DoF/s per V-cycle).  The same sol
 FP32 multigrid inside the FP64 CG is timed alongside, and the finest-level smoother kernel
 (the dominant kernel) is timed with HIP events on the launch stream for the roofline.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batch] [--extras]
 """
 import argparse
 import json
@@ -44,6 +44,23 @@ def time_events(fn, reps, torch):
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def measured_traffic():
+    """HBM bytes per finest-level smoother launch from the committed counter runs
+    (profiles/k_smooth_fp64_q4_32cube.traffic.json), or None when a kernel source listed
+    there has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_smooth_fp64_q4_32cube.traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    for rel, digest in rec["sources_sha256"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def cpu_baseline(dim, n, p, seed, budget_s=12.0):
@@ -126,6 +143,69 @@ def bench_batch(steps, torch, pmg, rhs_vector):
             "first_solve_s_incl_tuning": t_first}
 
 
+def _solve_times(torch, pmg, pr, b, precs, steps):
+    """Time-to-solution, iterations and relative residual of each multigrid precision, and
+    the relative difference of each solution to the FP64-multigrid one."""
+    out, xref = {}, None
+    for prec, name in precs:
+        x = torch.empty_like(b)
+        pmg.solve(pr, b, x, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = pmg.solve(pr, b, x, prec)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        N = pr.n_nodes[-1]
+        rec = {"time_to_solution_s": t, "iterations": info.iterations, "rel_residual": info.rel_residual,
+               "dof_per_s_per_vcycle": N * info.iterations / t}
+        if xref is None:
+            xref = x
+        else:
+            rec["solution_rel_diff_vs_fp64_mg"] = float(torch.linalg.vector_norm(x - xref) /
+                                                        torch.linalg.vector_norm(xref))
+        out[name] = rec
+    return out
+
+
+def bench_degree_sweep(torch, pmg, rhs_vector, steps):
+    """3D Poisson, 64^3 hexes, p = 2..8 (paper p-hierarchies), seeds 300 + p: FP64 and FP32
+    multigrid inside the FP64 flexible CG (on Cartesian meshes BF16 storage has no stored
+    operator data to act on, so it equals FP32)."""
+    res = []
+    for p in range(2, 9):
+        log(f"bench: degree sweep 64^3 Q{p}")
+        pr = pmg.make_problem(3, 64, p)
+        b = torch.as_tensor(rhs_vector(3, 64, p, 300 + p), dtype=torch.float64, device="cuda:0")
+        rec = {"degree": p, "n_dofs": pr.n_nodes[-1]}
+        rec.update(_solve_times(torch, pmg, pr, b, ((pmg.FP64, "fp64_mg"), (pmg.FP32, "fp32_mg")), steps))
+        res.append(rec)
+        del pr, b
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_general(torch, pmg, steps):
+    """3D variable coefficient on a perturbed mesh: 48^3 hexes, Q6, interior vertices moved
+    by 0.1 h, a = exp(seeded smooth field) in [0.1, 10]; FP64, FP32 and FP32 with bfloat16
+    operator storage inside the FP64 flexible CG."""
+    from paper_2512_02577_amd.inputs import CoefficientField, jittered_vertices, rhs_vector
+
+    log("bench: general path 48^3 Q6 (setup)")
+    t0 = time.perf_counter()
+    pr = pmg.make_problem(3, 48, 6, vertices=jittered_vertices(3, 48, 0.1, 40), coefficient=CoefficientField(3, 41))
+    t_setup = time.perf_counter() - t0
+    b = torch.as_tensor(rhs_vector(3, 48, 6, 4), dtype=torch.float64, device="cuda:0")
+    log("bench: general path solves")
+    rec = {"workload": "3D -div(a grad u) = f, 48^3 perturbed hexes (jitter 0.1 h), Q6, a in [0.1, 10]",
+           "n_dofs": pr.n_nodes[-1], "setup_s": t_setup}
+    rec.update(_solve_times(torch, pmg, pr, b, ((pmg.FP64, "fp64_mg"), (pmg.FP32, "fp32_mg"),
+                                                (pmg.FP32_BF16, "fp32_bf16_mg")), steps))
+    del pr, b
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +214,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true", help="leave out the 16-problem batch measurement")
+    ap.add_argument("--extras", action="store_true",
+                    help="also the 64^3 degree sweep and the 48^3 Q6 perturbed-mesh problem (minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -216,7 +298,8 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(ach_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach_tf / FP64_PEAK_TFLOPS, 4)}
-    roof.update({"traffic": None, "kernel": "k_smooth<3,double,4,{1,3,4}> (finest level, one color launch)",
+    traffic = measured_traffic()
+    roof.update({"traffic": traffic, "kernel": "k_smooth<3,double,4,{1,3,4}> (finest level, one color launch)",
                  "avg_launch_us": round(t_launch * 1e6, 2), "bytes_per_launch": bytes_launches // ncol,
                  "flops_per_launch": flops // ncol, "flop_per_byte": round(ai, 2),
                  "achieved_tflops": round(ach_tf, 3), "achieved_gbs": round(ach_gbs, 1)})
@@ -252,6 +335,9 @@ def main():
     if not args.no_batch:
         log("bench: 16-problem batch (FP32-MG in FP64 CG) and the same solves one by one")
         out["batched"] = bench_batch(max(1, min(args.steps, 3)), torch, pmg, rhs_vector)
+    if args.extras:
+        out["degree_sweep_64"] = bench_degree_sweep(torch, pmg, rhs_vector, max(1, min(args.steps, 2)))
+        out["general_48_q6"] = bench_general(torch, pmg, max(1, min(args.steps, 2)))
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline (8^3 cells, Q4, V-cycles, one thread)")
         rate, k, t = cpu_baseline(3, 8, 4, seed)

@@ -236,7 +236,7 @@ struct PatchBody {
     // other patch of the color has it in its closure), so the values the final update
     // adds to can be read now, with the gathers, instead of after the local solve.
     constexpr int NUI = (nd + NT - 1) / NT;
-    constexpr bool KEEP = NUI <= 2;
+    constexpr bool KEEP = NUI <= 3;
     T uold[KEEP ? NUI : 1];
     if constexpr (KEEP) {
 #pragma unroll

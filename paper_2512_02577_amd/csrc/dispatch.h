@@ -72,9 +72,6 @@ inline int hierarchy_code(int p, const int *deg, int L) {
 // Threads per workgroup of the patch kernel and of the apply kernel, by degree.
 constexpr int patch_threads(int p) { return p <= 2 ? 64 : (p <= 4 ? 128 : 256); }
 constexpr int apply_threads(int p) { return p <= 2 ? 128 : 128; }
-// Minimum waves per SIMD asked of the compiler for the patch kernel (register budget):
-// 3D FP64 p = 3, 4 fit 6 waves (80 VGPRs), which with their LDS arena gives 12 patches
-// per CU; elsewhere the compiler's choice.
-constexpr int smooth_waves(int dim, int tbytes, int p) { return dim == 3 && tbytes == 8 && (p == 3 || p == 4) ? 6 : 1; }
+
 
 }  // namespace pmg

@@ -23,7 +23,7 @@ __device__ inline T *lds_arena() {
 
 // ---- patch smoother: one workgroup per patch of one color ----
 template <int DIM, typename T, int P, class H>
-__global__ __launch_bounds__(patch_threads(P), smooth_waves(DIM, sizeof(T), P)) void k_smooth(SmoothArgs<T> a) {
+__global__ __launch_bounds__(patch_threads(P)) void k_smooth(SmoothArgs<T> a) {
   using B = PatchBody<DIM, T, patch_threads(P), P, H>;
   B::smooth_patch(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
