@@ -88,6 +88,43 @@ BATCH = [(16, 2), (24, 3), (32, 4), (48, 5), (16, 6), (24, 7), (32, 2), (48, 3),
          (16, 7), (24, 6), (32, 5), (48, 4)]
 
 
+# 16 small problems, where the per-launch and per-iteration costs of one-by-one solves dominate
+SMALL_BATCH = [(8, 2), (8, 3), (8, 4), (8, 5), (12, 2), (12, 3), (12, 4), (12, 6), (16, 2), (16, 3), (16, 4), (16, 7),
+               (6, 5), (6, 6), (6, 7), (4, 8)]
+
+
+def bench_small_batch(steps, torch, pmg, rhs_vector):
+    """16 small 3D problems (4^3..16^3 cells, Q2..Q8), FP32-MG in FP64 CG: batched vs one by one."""
+    dev = "cuda:0"
+    probs = [pmg.make_problem(3, n, p) for n, p in SMALL_BATCH]
+    bs = [torch.as_tensor(rhs_vector(3, n, p, 700 + k), dtype=torch.float64, device=dev)
+          for k, (n, p) in enumerate(SMALL_BATCH)]
+    xs = [torch.empty_like(b) for b in bs]
+    bt = pmg.batch_create(probs, os.path.join(ROOT, "paper_2512_02577_amd", "tuning", "launch_params.json"))
+    pmg.batch_solve(bt, bs, xs, pmg.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = pmg.batch_solve(bt, bs, xs, pmg.FP32)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    for pr, b, x in zip(probs, bs, xs):
+        pmg.solve(pr, b, x, pmg.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        its1 = [pmg.solve(pr, b, x, pmg.FP32).iterations for pr, b, x in zip(probs, bs, xs)]
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / steps
+    Ns = [pr.n_nodes[-1] for pr in probs]
+    its = [i.iterations for i in infos]
+    return {"problems": [f"{n}^3 Q{p}" for n, p in SMALL_BATCH], "n_dofs": sum(Ns),
+            "time_to_solution_s": t_batch, "one_by_one_time_s": t_seq, "speedup_vs_one_by_one": t_seq / t_batch,
+            "iterations": its, "one_by_one_iterations": its1,
+            "value": sum(N * k for N, k in zip(Ns, its)) / t_batch, "unit": "DoF/s per V-cycle",
+            "max_rel_residual": max(i.rel_residual for i in infos)}
+
+
 def bench_batch(steps, torch, pmg, rhs_vector):
     """The 16-problem batch: FP32 multigrid in FP64 flexible CG, all problems in one batch
     (persistent stage launches, graph-captured), against the same 16 solves one by one."""
@@ -335,6 +372,7 @@ def main():
     if not args.no_batch:
         log("bench: 16-problem batch (FP32-MG in FP64 CG) and the same solves one by one")
         out["batched"] = bench_batch(max(1, min(args.steps, 3)), torch, pmg, rhs_vector)
+        out["batched_small"] = bench_small_batch(max(1, min(args.steps, 3)), torch, pmg, rhs_vector)
     if args.extras:
         out["degree_sweep_64"] = bench_degree_sweep(torch, pmg, rhs_vector, max(1, min(args.steps, 2)))
         out["general_48_q6"] = bench_general(torch, pmg, max(1, min(args.steps, 2)))

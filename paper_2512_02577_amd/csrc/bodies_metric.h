@@ -142,15 +142,14 @@ struct QTabDev {
   const T *B, *BT, *Dq, *DqT, *Bpc, *Bpi, *BpiT, *Dqp, *DqpT;
 };
 
-// Scratch of metric_apply on a patch of degree Q with input extent E (closure or interior):
-// W1: max(NQ E^2, e NQ^2), W2: max(NQ^2 E, e^2 NQ), V, GX, GY, GZ: NQ^3 (2D analogues).
-template <int DIM, int Q, int E>
+// Scratch of metric_patch on a patch of degree Q: V, GX, GY (, GZ) of NQ^d Gauss-point
+// values each.  The interpolation stages to and from the Gauss points (at most NQ^d
+// values each) live in the gradient buffers, which are dead at those times.
+template <int DIM, int Q>
 struct MetricScratch {
-  static constexpr int NQ = 2 * (Q + 1), e = 2 * Q - 1;
-  static constexpr int w1 = DIM == 3 ? cmax(NQ * E * E, e * NQ * NQ) : cmax(NQ * E, e * NQ);
-  static constexpr int w2 = DIM == 3 ? cmax(NQ * NQ * E, e * e * NQ) : 0;
+  static constexpr int NQ = 2 * (Q + 1);
   static constexpr int q3 = ipow(NQ, DIM);
-  static constexpr int total = w1 + w2 + (DIM == 3 ? 4 : 3) * q3;
+  static constexpr int total = (DIM == 3 ? 4 : 3) * q3;
 };
 
 // out = base - A_patch in, with A evaluated through the Gauss points of the patch's cells.
@@ -159,8 +158,12 @@ template <int DIM, int Q, class PB, int NT, typename T, typename S>
 PMG_INLINE void metric_patch(int tid, const T *in, T *out, const T *base, const QTabDev<T> &tb, const S *G, int n,
                              const int c0[3], T *scr) {
   constexpr int E = PB::nin, NQ = 2 * (Q + 1), nq = Q + 1, e = 2 * Q - 1;
-  using SC = MetricScratch<DIM, Q, E>;
-  T *w1 = scr, *w2 = scr + SC::w1, *V = w2 + SC::w2, *gx = V + SC::q3, *gy = gx + SC::q3, *gz = gy + SC::q3;
+  using SC = MetricScratch<DIM, Q>;
+  T *V = scr, *gx = V + SC::q3, *gy = gx + SC::q3, *gz = gy + SC::q3;
+  static_assert(DIM == 2 || (NQ * E * E <= SC::q3 && NQ * NQ * E <= SC::q3 && e * NQ * NQ <= SC::q3),
+                "interpolation stages must fit a gradient buffer");
+  // interpolation to the Gauss points: stages in gy, gz; back to the nodes: stages in gx, gy
+  T *w1 = gy, *w2 = DIM == 3 ? gz : nullptr, *b1 = gx, *b2 = gy;
   const T *Bin = std::is_same<PB, PatBpc<Q>>::value ? tb.Bpc : tb.Bpi;
   if constexpr (DIM == 3) {
     contract1<0, E, E, E, PB, NT, false>(tid, in, w1, Bin);
@@ -181,11 +184,11 @@ PMG_INLINE void metric_patch(int tid, const T *in, T *out, const T *base, const 
     PMG_SYNC();
     contract1<2, NQ, NQ, NQ, PatDqp<Q>, NT, true>(tid, gz, V, tb.DqpT);
     PMG_SYNC();
-    contract1<0, NQ, NQ, NQ, PatBpiT<Q>, NT, false>(tid, V, w1, tb.BpiT);
+    contract1<0, NQ, NQ, NQ, PatBpiT<Q>, NT, false>(tid, V, b1, tb.BpiT);
     PMG_SYNC();
-    contract1<1, e, NQ, NQ, PatBpiT<Q>, NT, false>(tid, w1, w2, tb.BpiT);
+    contract1<1, e, NQ, NQ, PatBpiT<Q>, NT, false>(tid, b1, b2, tb.BpiT);
     PMG_SYNC();
-    contract_sub<2, e, e, NQ, PatBpiT<Q>, NT>(tid, w2, out, base, tb.BpiT);
+    contract_sub<2, e, e, NQ, PatBpiT<Q>, NT>(tid, b2, out, base, tb.BpiT);
   } else {
     contract1<0, E, E, 1, PB, NT, false>(tid, in, w1, Bin);
     PMG_SYNC();
@@ -200,9 +203,9 @@ PMG_INLINE void metric_patch(int tid, const T *in, T *out, const T *base, const 
     PMG_SYNC();
     contract1<1, NQ, NQ, 1, PatDqp<Q>, NT, true>(tid, gy, V, tb.DqpT);
     PMG_SYNC();
-    contract1<0, NQ, NQ, 1, PatBpiT<Q>, NT, false>(tid, V, w1, tb.BpiT);
+    contract1<0, NQ, NQ, 1, PatBpiT<Q>, NT, false>(tid, V, b1, tb.BpiT);
     PMG_SYNC();
-    contract_sub<1, e, NQ, 1, PatBpiT<Q>, NT>(tid, w1, out, base, tb.BpiT);
+    contract_sub<1, e, NQ, 1, PatBpiT<Q>, NT>(tid, b1, out, base, tb.BpiT);
   }
 }
 
@@ -240,12 +243,8 @@ struct MetricPatchBody {
   static constexpr int qd(int l) { return H::q[l]; }
   static constexpr int nl(int l) { return 2 * H::q[l] - 1; }
   static constexpr int ndl(int l) { return ipow(2 * H::q[l] - 1, DIM); }
-  static constexpr int scratch(int l, int E) {
-    // MetricScratch<DIM, q, E>::total written out for a runtime level index
-    return (DIM == 3 ? cmax(2 * (qd(l) + 1) * E * E, nl(l) * 4 * (qd(l) + 1) * (qd(l) + 1))
-                     : cmax(2 * (qd(l) + 1) * E, nl(l) * 2 * (qd(l) + 1))) +
-           (DIM == 3 ? cmax(4 * (qd(l) + 1) * (qd(l) + 1) * E, nl(l) * nl(l) * 2 * (qd(l) + 1)) : 0) +
-           (DIM == 3 ? 4 : 3) * ipow(2 * (qd(l) + 1), DIM);
+  static constexpr int scratch(int l) {  // MetricScratch<DIM, q_l>::total
+    return (DIM == 3 ? 4 : 3) * ipow(2 * (qd(l) + 1), DIM);
   }
   static constexpr int transfer_scratch(int l) {
     return l == 0 ? 0
@@ -253,18 +252,22 @@ struct MetricPatchBody {
                          kron_t1(DIM, nl(l - 1), nl(l)) + kron_t2(DIM, nl(l - 1), nl(l)));
   }
   static constexpr int scr_size() {
-    int s = scratch(L - 1, N);
-    for (int l = 1; l < L; ++l) s = cmax(s, cmax(scratch(l, nl(l)), transfer_scratch(l)));
+    int s = scratch(L - 1);
+    for (int l = 1; l < L; ++l) s = cmax(s, cmax(scratch(l), transfer_scratch(l)));
     return s;
   }
-  // layout: r | d | c | ucl | lower r_l, d_l | res | scratch
-  static constexpr int off_r = 0, off_d = nd, off_cc = 2 * nd, off_ucl = 3 * nd;
+  // layout: r | d | ucl | lower r_l, d_l | res | scratch | c (Richardson steps after the
+  // first only, so that one step needs `size1`)
+  static constexpr int off_r = 0, off_d = nd, off_ucl = 2 * nd;
   static constexpr int lower_size(int l) { return l < 0 ? 0 : 2 * ndl(l) + lower_size(l - 1); }
-  static constexpr int off_lr(int l) { return 3 * nd + Nd + (l == 0 ? 0 : lower_size(l - 1)); }
+  static constexpr int off_lr(int l) { return 2 * nd + Nd + (l == 0 ? 0 : lower_size(l - 1)); }
   static constexpr int off_ld(int l) { return off_lr(l) + ndl(l); }
-  static constexpr int off_res = 3 * nd + Nd + lower_size(L - 2);
+  static constexpr int off_res = 2 * nd + Nd + lower_size(L - 2);
   static constexpr int off_scr = off_res + nd;
-  static constexpr int size = off_scr + scr_size();
+  static constexpr int size1 = off_scr + scr_size();
+  static constexpr int off_cc = size1;
+  static constexpr int size = size1 + nd;
+  PMG_HD static constexpr int arena(int n_iter) { return n_iter > 1 ? size : size1; }
 
   template <int l>
   PMG_INLINE static void vmult_residual(int tid, T *lds, const MetricSmoothArgs<T, S> &a, const int c0[3],

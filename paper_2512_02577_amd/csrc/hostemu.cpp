@@ -162,7 +162,7 @@ struct EmuMetricSmooth {
   struct F {
     static int run(const MetricSmoothArgs<double, double> &base, int n, int color_dir, bool local_only, int nb) {
       using B = MetricPatchBody<DIM, double, double, 1, P, H>;
-      std::vector<double> lds(B::size);
+      std::vector<double> lds(B::arena(base.n_iter));  // exactly what the device launch gets
       if (local_only) {
         for (int blk = 0; blk < nb; ++blk) B::local_only(0, blk, lds.data(), base);
         return 0;

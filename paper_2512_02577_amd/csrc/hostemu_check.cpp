@@ -13,6 +13,11 @@ int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const doubl
 int pmgemu_apply(int dim, int n, int p, int resid, const double *u, const double *b, double *out);
 int pmgemu_transfer(int dim, int nc, int p, int restrict_, const double *in, double *out);
 int pmgemu_coarse_solve(int dim, int n0, int p, const double *r, double *z);
+int pmgemu_metric_apply(int dim, int n, int p, const double *verts, const double *coef, int resid, const double *u,
+                        const double *b, double *out);
+int pmgemu_metric_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
+                         int color_dir, const double *verts, const double *const *coefs, double *u, const double *b,
+                         int nb, const double *r, double *d);
 }
 
 static std::vector<double> rnd(size_t n, unsigned seed) {
@@ -68,6 +73,23 @@ int main() {
         }
         std::printf("dim %d p %d hierarchy %d ok\n", dim, p, code);
       }
+  // general path (Cartesian vertices through the metric code, mu = 1), paper hierarchies
+  for (int dim = 2; dim <= 3; ++dim)
+    for (int p = 1; p <= 8; ++p) {
+      if (dim == 3 && p > 6) continue;
+      std::vector<int> deg;
+      for (int x = 1; x < p; x = 2 * x + 1) deg.push_back(x);
+      deg.push_back(p);
+      std::vector<double> om(deg.size(), 0.6);
+      const int n = 2;
+      const long N = ipow((long)p * n + 1, dim);
+      auto u = rnd(N, 5), b = rnd(N, 6), out = std::vector<double>(N);
+      fails += pmgemu_metric_apply(dim, n, p, nullptr, nullptr, 1, u.data(), b.data(), out.data()) != 0;
+      for (int it = 1; it <= 2; ++it)
+        fails += pmgemu_metric_smooth(dim, n, p, deg.data(), (int)deg.size(), om.data(), it - 1, it, 1, nullptr,
+                                      nullptr, u.data(), b.data(), 0, nullptr, nullptr) != 0;
+      std::printf("general dim %d p %d ok\n", dim, p);
+    }
   std::printf("failures: %d\n", fails);
   return fails != 0;
 }

@@ -90,7 +90,7 @@ int launch_arena(KL klds, KG kglob, int nblk, int threads, size_t bytes, const A
     if (bytes > 65536) {
       static thread_local const void *last = nullptr;
       if (last != (const void *)klds) {
-        if (hipFuncSetAttribute((const void *)klds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+        if (hipFuncSetAttribute((const void *)klds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ar.lds_max) !=
             hipSuccess)
           return -4;
         last = (const void *)klds;
@@ -108,7 +108,7 @@ struct SmoothF {
     static int run(const MetricSmoothArgs<T, S> &a, const Arena &ar, hipStream_t s) {
       using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>;
       return launch_arena(k_msmooth<DIM, T, S, P, H>, k_msmooth_g<DIM, T, S, P, H>, a.n_patch,
-                          metric_patch_threads(P), B::size * sizeof(T), ar, s, a);
+                          metric_patch_threads(P), B::arena(a.n_iter) * sizeof(T), ar, s, a);
     }
   };
 };
@@ -120,7 +120,7 @@ struct LocalF {
     static int run(const MetricSmoothArgs<T, S> &a, int nb, const Arena &ar, hipStream_t s) {
       using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>;
       return launch_arena(k_mlocal<DIM, T, S, P, H>, k_mlocal_g<DIM, T, S, P, H>, nb, metric_patch_threads(P),
-                          B::size * sizeof(T), ar, s, a, nb);
+                          B::arena(a.n_iter) * sizeof(T), ar, s, a, nb);
     }
   };
 };
