@@ -142,14 +142,17 @@ struct QTabDev {
   const T *B, *BT, *Dq, *DqT, *Bpc, *Bpi, *BpiT, *Dqp, *DqpT;
 };
 
-// Scratch of metric_patch on a patch of degree Q: V, GX, GY (, GZ) of NQ^d Gauss-point
-// values each.  The interpolation stages to and from the Gauss points (at most NQ^d
-// values each) live in the gradient buffers, which are dead at those times.
+// Scratch of metric_patch on a patch of degree Q: three (2D: two) buffers A, B, C of NQ^d
+// Gauss-point values.  The interpolation stages to the Gauss points run through B and C,
+// the values land in A; the y and z reference derivatives go to B and C, the x derivative
+// replaces the values in A (in place along x); the flux is formed in place; the
+// transposed derivatives accumulate in A (x in place first); the stages back to the nodes
+// run through B and C.
 template <int DIM, int Q>
 struct MetricScratch {
   static constexpr int NQ = 2 * (Q + 1);
   static constexpr int q3 = ipow(NQ, DIM);
-  static constexpr int total = (DIM == 3 ? 4 : 3) * q3;
+  static constexpr int total = (DIM == 3 ? 3 : 2) * q3;
 };
 
 // out = base - A_patch in, with A evaluated through the Gauss points of the patch's cells.
@@ -159,53 +162,55 @@ PMG_INLINE void metric_patch(int tid, const T *in, T *out, const T *base, const 
                              const int c0[3], T *scr) {
   constexpr int E = PB::nin, NQ = 2 * (Q + 1), nq = Q + 1, e = 2 * Q - 1;
   using SC = MetricScratch<DIM, Q>;
-  T *V = scr, *gx = V + SC::q3, *gy = gx + SC::q3, *gz = gy + SC::q3;
+  using PD = PatDqp<Q>;
+  using PT = PatBpiT<Q>;
+  T *A = scr, *B = scr + SC::q3, *C = DIM == 3 ? scr + 2 * SC::q3 : nullptr;
   static_assert(DIM == 2 || (NQ * E * E <= SC::q3 && NQ * NQ * E <= SC::q3 && e * NQ * NQ <= SC::q3),
-                "interpolation stages must fit a gradient buffer");
-  // interpolation to the Gauss points: stages in gy, gz; back to the nodes: stages in gx, gy
-  T *w1 = gy, *w2 = DIM == 3 ? gz : nullptr, *b1 = gx, *b2 = gy;
+                "interpolation stages must fit a Gauss-point buffer");
   const T *Bin = std::is_same<PB, PatBpc<Q>>::value ? tb.Bpc : tb.Bpi;
   if constexpr (DIM == 3) {
-    contract1<0, E, E, E, PB, NT, false>(tid, in, w1, Bin);
+    dcontract1<0, E, E, E, PB, NT, false>(tid, in, B, Bin);
     PMG_SYNC();
-    contract1<1, NQ, E, E, PB, NT, false>(tid, w1, w2, Bin);
+    dcontract1<1, NQ, E, E, PB, NT, false>(tid, B, C, Bin);
     PMG_SYNC();
-    contract1<2, NQ, NQ, E, PB, NT, false>(tid, w2, V, Bin);
+    dcontract1<2, NQ, NQ, E, PB, NT, false>(tid, C, A, Bin);  // values at the Gauss points
     PMG_SYNC();
-    contract1<0, NQ, NQ, NQ, PatDqp<Q>, NT, false>(tid, V, gx, tb.Dqp);
-    contract1<1, NQ, NQ, NQ, PatDqp<Q>, NT, false>(tid, V, gy, tb.Dqp);
-    contract1<2, NQ, NQ, NQ, PatDqp<Q>, NT, false>(tid, V, gz, tb.Dqp);
+    dcontract1<1, NQ, NQ, NQ, PD, NT, false>(tid, A, B, tb.Dqp);
+    dcontract1<2, NQ, NQ, NQ, PD, NT, false>(tid, A, C, tb.Dqp);
     PMG_SYNC();
-    flux<3, NQ, nq, NT>(tid, gx, gy, gz, G, n, c0);
+    dcontract1<0, NQ, NQ, NQ, PD, NT, false, true>(tid, A, A, tb.Dqp);
     PMG_SYNC();
-    contract1<0, NQ, NQ, NQ, PatDqp<Q>, NT, false>(tid, gx, V, tb.DqpT);
+    flux<3, NQ, nq, NT>(tid, A, B, C, G, n, c0);
     PMG_SYNC();
-    contract1<1, NQ, NQ, NQ, PatDqp<Q>, NT, true>(tid, gy, V, tb.DqpT);
+    dcontract1<0, NQ, NQ, NQ, PD, NT, false, true>(tid, A, A, tb.DqpT);
     PMG_SYNC();
-    contract1<2, NQ, NQ, NQ, PatDqp<Q>, NT, true>(tid, gz, V, tb.DqpT);
+    dcontract1<1, NQ, NQ, NQ, PD, NT, true>(tid, B, A, tb.DqpT);
     PMG_SYNC();
-    contract1<0, NQ, NQ, NQ, PatBpiT<Q>, NT, false>(tid, V, b1, tb.BpiT);
+    dcontract1<2, NQ, NQ, NQ, PD, NT, true>(tid, C, A, tb.DqpT);
     PMG_SYNC();
-    contract1<1, e, NQ, NQ, PatBpiT<Q>, NT, false>(tid, b1, b2, tb.BpiT);
+    dcontract1<0, NQ, NQ, NQ, PT, NT, false>(tid, A, B, tb.BpiT);
     PMG_SYNC();
-    contract_sub<2, e, e, NQ, PatBpiT<Q>, NT>(tid, b2, out, base, tb.BpiT);
+    dcontract1<1, e, NQ, NQ, PT, NT, false>(tid, B, C, tb.BpiT);
+    PMG_SYNC();
+    dcontract_sub<2, e, e, NQ, PT, NT>(tid, C, out, base, tb.BpiT);
   } else {
-    contract1<0, E, E, 1, PB, NT, false>(tid, in, w1, Bin);
+    dcontract1<0, E, E, 1, PB, NT, false>(tid, in, B, Bin);
     PMG_SYNC();
-    contract1<1, NQ, E, 1, PB, NT, false>(tid, w1, V, Bin);
+    dcontract1<1, NQ, E, 1, PB, NT, false>(tid, B, A, Bin);
     PMG_SYNC();
-    contract1<0, NQ, NQ, 1, PatDqp<Q>, NT, false>(tid, V, gx, tb.Dqp);
-    contract1<1, NQ, NQ, 1, PatDqp<Q>, NT, false>(tid, V, gy, tb.Dqp);
+    dcontract1<1, NQ, NQ, 1, PD, NT, false>(tid, A, B, tb.Dqp);
     PMG_SYNC();
-    flux<2, NQ, nq, NT>(tid, gx, gy, gz, G, n, c0);
+    dcontract1<0, NQ, NQ, 1, PD, NT, false, true>(tid, A, A, tb.Dqp);
     PMG_SYNC();
-    contract1<0, NQ, NQ, 1, PatDqp<Q>, NT, false>(tid, gx, V, tb.DqpT);
+    flux<2, NQ, nq, NT>(tid, A, B, B, G, n, c0);
     PMG_SYNC();
-    contract1<1, NQ, NQ, 1, PatDqp<Q>, NT, true>(tid, gy, V, tb.DqpT);
+    dcontract1<0, NQ, NQ, 1, PD, NT, false, true>(tid, A, A, tb.DqpT);
     PMG_SYNC();
-    contract1<0, NQ, NQ, 1, PatBpiT<Q>, NT, false>(tid, V, b1, tb.BpiT);
+    dcontract1<1, NQ, NQ, 1, PD, NT, true>(tid, B, A, tb.DqpT);
     PMG_SYNC();
-    contract_sub<1, e, NQ, 1, PatBpiT<Q>, NT>(tid, b1, out, base, tb.BpiT);
+    dcontract1<0, NQ, NQ, 1, PT, NT, false>(tid, A, B, tb.BpiT);
+    PMG_SYNC();
+    dcontract_sub<1, e, NQ, 1, PT, NT>(tid, B, out, base, tb.BpiT);
   }
 }
 
@@ -244,7 +249,7 @@ struct MetricPatchBody {
   static constexpr int nl(int l) { return 2 * H::q[l] - 1; }
   static constexpr int ndl(int l) { return ipow(2 * H::q[l] - 1, DIM); }
   static constexpr int scratch(int l) {  // MetricScratch<DIM, q_l>::total
-    return (DIM == 3 ? 4 : 3) * ipow(2 * (qd(l) + 1), DIM);
+    return (DIM == 3 ? 3 : 2) * ipow(2 * (qd(l) + 1), DIM);
   }
   static constexpr int transfer_scratch(int l) {
     return l == 0 ? 0
@@ -256,18 +261,38 @@ struct MetricPatchBody {
     for (int l = 1; l < L; ++l) s = cmax(s, cmax(scratch(l), transfer_scratch(l)));
     return s;
   }
-  // layout: r | d | ucl | lower r_l, d_l | res | scratch | c (Richardson steps after the
-  // first only, so that one step needs `size1`)
+  // layout: r | d | lower r_l, d_l | res | scratch | c (Richardson steps after the first
+  // only, so that one step needs `size1`).  The closure values ucl (phase R only) overlay
+  // lower, res and the start of the scratch: the first interpolation stage reads ucl and
+  // writes the second scratch buffer, beyond ucl.
   static constexpr int off_r = 0, off_d = nd, off_ucl = 2 * nd;
   static constexpr int lower_size(int l) { return l < 0 ? 0 : 2 * ndl(l) + lower_size(l - 1); }
-  static constexpr int off_lr(int l) { return 2 * nd + Nd + (l == 0 ? 0 : lower_size(l - 1)); }
+  static constexpr int off_lr(int l) { return 2 * nd + (l == 0 ? 0 : lower_size(l - 1)); }
   static constexpr int off_ld(int l) { return off_lr(l) + ndl(l); }
-  static constexpr int off_res = 2 * nd + Nd + lower_size(L - 2);
+  static constexpr int off_res = 2 * nd + lower_size(L - 2);
   static constexpr int off_scr = off_res + nd;
+  static_assert(off_ucl + Nd <= off_scr + ipow(2 * (P + 1), DIM), "closure must end before the stage-1 buffer");
   static constexpr int size1 = off_scr + scr_size();
   static constexpr int off_cc = size1;
   static constexpr int size = size1 + nd;
   PMG_HD static constexpr int arena(int n_iter) { return n_iter > 1 ? size : size1; }
+
+  // out (=|+=) Kronecker product of Mat in every direction, on compact tensors
+  template <class Pat, bool ADD>
+  PMG_INLINE static void kron_dense(int tid, const T *in, T *out, const T *Mat, T *t1, T *t2) {
+    constexpr int I = Pat::nin, O = Pat::nout;
+    if constexpr (DIM == 3) {
+      dcontract1<0, I, I, I, Pat, NT, false>(tid, in, t1, Mat);
+      PMG_SYNC();
+      dcontract1<1, O, I, I, Pat, NT, false>(tid, t1, t2, Mat);
+      PMG_SYNC();
+      dcontract1<2, O, O, I, Pat, NT, ADD>(tid, t2, out, Mat);
+    } else {
+      dcontract1<0, I, I, 1, Pat, NT, false>(tid, in, t1, Mat);
+      PMG_SYNC();
+      dcontract1<1, O, I, 1, Pat, NT, ADD>(tid, t1, out, Mat);
+    }
+  }
 
   template <int l>
   PMG_INLINE static void vmult_residual(int tid, T *lds, const MetricSmoothArgs<T, S> &a, const int c0[3],
@@ -292,10 +317,10 @@ struct MetricPatchBody {
       PMG_SYNC();
       T *rc = lds + off_lr(l - 1), *dc = lds + off_ld(l - 1);
       T *t1 = lds + off_scr, *t2 = t1 + t1size;
-      kron_all<DIM, PatRestrict<q, qc>, NT, false>(tid, res, rc, a.lev[l].TpT, t1, t2);
+      kron_dense<PatRestrict<q, qc>, false>(tid, res, rc, a.lev[l].TpT, t1, t2);
       PMG_SYNC();
       cycle<l - 1>(tid, lds, a, pidx, c0, rc, dc, full);
-      kron_all<DIM, PatProlong<q, qc>, NT, true>(tid, dc, d, a.lev[l].Tp, t1, t2);
+      kron_dense<PatProlong<q, qc>, true>(tid, dc, d, a.lev[l].Tp, t1, t2);
       PMG_SYNC();
       if (full) {
         vmult_residual<l>(tid, lds, a, c0, d, r, res);

@@ -14,7 +14,9 @@ namespace pmg {
 
 namespace mdetail {
 
-constexpr int metric_patch_threads(int p) { return p <= 2 ? 128 : 256; }
+// Lanes per patch: FP64 patches of degree >= 5 fit one per CU in LDS, so they get 8 waves
+// (the short stages split their outputs over them).
+constexpr int metric_patch_threads(int p, int tbytes) { return p <= 2 ? 128 : (tbytes == 8 && p >= 5 ? 512 : 256); }
 constexpr int metric_apply_threads(int p) { return p <= 3 ? 128 : 256; }
 
 template <typename T>
@@ -24,14 +26,14 @@ __device__ inline T *lds_arena() {
 }
 
 template <int DIM, typename T, typename S, int P, class H>
-__global__ __launch_bounds__(metric_patch_threads(P)) void k_msmooth(MetricSmoothArgs<T, S> a) {
-  using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>;
+__global__ __launch_bounds__(metric_patch_threads(P, sizeof(T))) void k_msmooth(MetricSmoothArgs<T, S> a) {
+  using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>;
   B::smooth_patch(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
 template <int DIM, typename T, typename S, int P, class H>
-__global__ __launch_bounds__(metric_patch_threads(P)) void k_msmooth_g(MetricSmoothArgs<T, S> a, void *garena) {
-  using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>;
+__global__ __launch_bounds__(metric_patch_threads(P, sizeof(T))) void k_msmooth_g(MetricSmoothArgs<T, S> a, void *garena) {
+  using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>;
   T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
   for (int blk = blockIdx.x; blk < a.n_patch; blk += gridDim.x) {
     B::smooth_patch(threadIdx.x, blk, ar, a);
@@ -40,15 +42,15 @@ __global__ __launch_bounds__(metric_patch_threads(P)) void k_msmooth_g(MetricSmo
 }
 
 template <int DIM, typename T, typename S, int P, class H>
-__global__ __launch_bounds__(metric_patch_threads(P)) void k_mlocal(MetricSmoothArgs<T, S> a, int nb) {
-  using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>;
+__global__ __launch_bounds__(metric_patch_threads(P, sizeof(T))) void k_mlocal(MetricSmoothArgs<T, S> a, int nb) {
+  using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>;
   B::local_only(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
 template <int DIM, typename T, typename S, int P, class H>
-__global__ __launch_bounds__(metric_patch_threads(P)) void k_mlocal_g(MetricSmoothArgs<T, S> a, int nb,
+__global__ __launch_bounds__(metric_patch_threads(P, sizeof(T))) void k_mlocal_g(MetricSmoothArgs<T, S> a, int nb,
                                                                        void *garena) {
-  using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>;
+  using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>;
   T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
   for (int blk = blockIdx.x; blk < nb; blk += gridDim.x) {
     B::local_only(threadIdx.x, blk, ar, a);
@@ -106,9 +108,9 @@ struct SmoothF {
   template <int P, class H>
   struct F {
     static int run(const MetricSmoothArgs<T, S> &a, const Arena &ar, hipStream_t s) {
-      using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>;
+      using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>;
       return launch_arena(k_msmooth<DIM, T, S, P, H>, k_msmooth_g<DIM, T, S, P, H>, a.n_patch,
-                          metric_patch_threads(P), B::arena(a.n_iter) * sizeof(T), ar, s, a);
+                          metric_patch_threads(P, sizeof(T)), B::arena(a.n_iter) * sizeof(T), ar, s, a);
     }
   };
 };
@@ -118,8 +120,8 @@ struct LocalF {
   template <int P, class H>
   struct F {
     static int run(const MetricSmoothArgs<T, S> &a, int nb, const Arena &ar, hipStream_t s) {
-      using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>;
-      return launch_arena(k_mlocal<DIM, T, S, P, H>, k_mlocal_g<DIM, T, S, P, H>, nb, metric_patch_threads(P),
+      using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>;
+      return launch_arena(k_mlocal<DIM, T, S, P, H>, k_mlocal_g<DIM, T, S, P, H>, nb, metric_patch_threads(P, sizeof(T)),
                           B::arena(a.n_iter) * sizeof(T), ar, s, a, nb);
     }
   };
@@ -130,7 +132,7 @@ struct PatchBytesF {
   template <int P, class H>
   struct F {
     static int run(size_t *out) {
-      *out = MetricPatchBody<DIM, T, S, metric_patch_threads(P), P, H>::size * sizeof(T);
+      *out = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>::size * sizeof(T);
       return 0;
     }
   };

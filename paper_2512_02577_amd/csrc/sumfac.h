@@ -516,6 +516,55 @@ PMG_INLINE void scontract1(int tid, const T *in, T *out, const T *Mat_) {
   WSplit<F::X::NPEN, Pat::nout, NT>::template each<INPL>(tid, F{in, out, as_const(Mat_)});
 }
 
+template <int AX, int E0, int E1, int E2, class Pat, class LI, class LO, typename T>
+struct FCSub {  // out = base - Mat in
+  using X = Pen<AX, E0, E1, E2>;
+  const T *in;
+  T *out;
+  const T *base;
+  cptr<T> Mat;
+  struct Regs {
+    T v[Pat::nin];
+  };
+  PMG_INLINE void load(int pen, Regs &r) const {
+    const int ib = X::template base<LI>(pen);
+#pragma unroll
+    for (int i = 0; i < Pat::nin; ++i) r.v[i] = in[ib + i * X::template step<LI>()];
+  }
+  template <int O0, int O1>
+  PMG_INLINE void store(int pen, const Regs &r) const {
+    const int ob = X::template base<LO>(pen);
+#pragma unroll
+    for (int o = O0; o < O1; ++o) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < Pat::nin; ++i)
+        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * r.v[i];
+      const int oi = ob + o * X::template step<LO>();
+      out[oi] = base[oi] - acc;
+    }
+  }
+};
+
+// Compact tensors: the layout of the input (E0, E1, E2) and of the output along AX.
+template <int AX, int E0, int E1, int NOUT>
+using DenseOut = Dense<AX == 0 ? NOUT : E0, AX == 1 ? NOUT : E1>;
+
+// out (=|+=) Mat in on compact tensors (out-of-place, or in place along AX with INPL and
+// NOUT = NIN), split over waves like the strided contractions
+template <int AX, int E0, int E1, int E2, class Pat, int NT, bool ADD, bool INPL = false, typename T>
+PMG_INLINE void dcontract1(int tid, const T *in, T *out, const T *Mat) {
+  scontract1<AX, E0, E1, E2, Pat, NT, ADD, Dense<E0, E1>, DenseOut<AX, E0, E1, Pat::nout>, INPL>(tid, in, out, Mat);
+}
+
+// out = base - Mat in on compact tensors (out-of-place)
+template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
+PMG_INLINE void dcontract_sub(int tid, const T *in, T *out, const T *base, const T *Mat_) {
+  using F = FCSub<AX, E0, E1, E2, Pat, Dense<E0, E1>, DenseOut<AX, E0, E1, Pat::nout>, T>;
+  static_assert(F::X::NIN == Pat::nin, "extent mismatch");
+  WSplit<F::X::NPEN, Pat::nout, NT>::template each<false>(tid, F{in, out, base, as_const(Mat_)});
+}
+
 // Sum over the workgroup of one value per lane; every lane gets the total.  red: NT/64
 // (at least 1) elements of LDS scratch.  On the host (NT = 1) the value itself.
 template <int NT, typename T>
