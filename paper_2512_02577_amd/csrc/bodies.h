@@ -130,7 +130,23 @@ struct PatchBody {
     } else {
       constexpr int q = qd(l), qc = qd(l - 1), m = nl(l), mc = nl(l - 1), ndq = ndl(l);
       const cptr<T> invD = as_const(tb.invD[l]);
-      for (int e = tid; e < ndq; e += NT) d[e] = cinv * invD[e] * r[e];  // pre-smoothing
+      lane_gather<ndq, NT, 16, T>(  // pre-smoothing d = cinv D^-1 r
+          tid, [&](int e) { return invD[e]; }, [&](int e, T x) { d[e] = cinv * x * r[e]; });
+      // on p-level 1 the weights of the one-node coarsest level are read now, so that their
+      // loads overlap the residual below
+      constexpr int R1 = l == 1 ? (ndq + NT - 1) / NT : 1;
+      T wp[R1], tp[R1];
+      if constexpr (l == 1) {
+        const cptr<T> w = as_const(tb.TpT[l]), t = as_const(tb.Tp[l]);
+#pragma unroll
+        for (int j = 0; j < R1; ++j) {
+          const int e = tid + j * NT;
+          int k[3];
+          decode_l(e < ndq ? e : ndq - 1, m, k);
+          wp[j] = w[k[0]] * w[k[1]] * (DIM == 3 ? w[k[2]] : T(1));
+          tp[j] = t[k[0]] * t[k[1]] * (DIM == 3 ? t[k[2]] : T(1));
+        }
+      }
       PMG_SYNC();
       T *res = lds + off_X;
       vmult_residual<l>(tid, lds, tb, c, d, r, res);  // res = r - A d
@@ -138,21 +154,18 @@ struct PatchBody {
       if constexpr (l == 1) {
         // the coarsest p-level has one node: restriction is a weighted sum, its exact
         // solve a scalar, and prolongation the outer product of the embedding column
-        const cptr<T> w = as_const(tb.TpT[l]), t = as_const(tb.Tp[l]);
         T part = 0;
-        for (int e = tid; e < ndq; e += NT) {
-          int k[3];
-          decode_l(e, m, k);
-          const T wk = DIM == 3 ? w[k[2]] : T(1);
-          part += w[k[0]] * w[k[1]] * wk * res[e];
+#pragma unroll
+        for (int j = 0; j < R1; ++j) {
+          const int e = tid + j * NT;
+          if (e < ndq) part += wp[j] * res[e];
         }
         const T r0 = block_sum<NT>(tid, part, lds + off_red);
         const T d0 = cinv * as_const(tb.invD[0])[0] * r0;
-        for (int e = tid; e < ndq; e += NT) {
-          int k[3];
-          decode_l(e, m, k);
-          const T tk = DIM == 3 ? t[k[2]] : T(1);
-          d[e] += t[k[0]] * t[k[1]] * tk * d0;
+#pragma unroll
+        for (int j = 0; j < R1; ++j) {
+          const int e = tid + j * NT;
+          if (e < ndq) d[e] += tp[j] * d0;
         }
         PMG_SYNC();
       } else {
@@ -191,7 +204,8 @@ struct PatchBody {
       if (full) {  // post-smoothing
         vmult_residual<l>(tid, lds, tb, c, d, r, res);
         PMG_SYNC();
-        for (int e = tid; e < ndq; e += NT) d[e] += cinv * invD[e] * res[e];
+        lane_gather<ndq, NT, 16, T>(
+            tid, [&](int e) { return invD[e]; }, [&](int e, T x) { d[e] += cinv * x * res[e]; });
         PMG_SYNC();
       }
     }
@@ -242,17 +256,24 @@ struct PatchBody {
 #pragma unroll
       for (int k = 0; k < NUI; ++k) {
         const int e = tid + k * NT;
-        if (e < nd) uold[k] = u_in[interior_index(e, g0, m)];
+        uold[k] = u_in[interior_index(e < nd ? e : nd - 1, g0, m)];
       }
     }
-    for (int e = tid; e < Nd; e += NT) {
-      const int i = e % N, j = (e / N) % N, k = DIM == 3 ? e / (N * N) : 0;
-      const int gx = g0[0] + i, gy = g0[1] + j, gz = g0[2] + k;
-      bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
-      if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
-      ucl[e] = bnd ? T(0) : u_in[gx + m * (gy + m * gz)];
-    }
-    for (int e = tid; e < nd; e += NT) r[e] = a.b[interior_index(e, g0, m)];
+    // closure of u (zero on the Dirichlet boundary; every closure node lies inside the
+    // mesh, so the load itself is always valid) and the interior of b
+    const T *__restrict__ b_in = a.b;
+    lane_gather2<Nd, nd, NT, 16, T>(
+        tid,
+        [&](int e) {
+          const int i = e % N, j = (e / N) % N, k = DIM == 3 ? e / (N * N) : 0;
+          const int gx = g0[0] + i, gy = g0[1] + j, gz = g0[2] + k;
+          bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
+          if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
+          const T x = u_in[gx + m * (gy + m * gz)];
+          return bnd ? T(0) : x;
+        },
+        [&](int e, T x) { ucl[e] = x; }, [&](int e) { return b_in[interior_index(e, g0, m)]; },
+        [&](int e, T x) { r[e] = x; });
     PMG_SYNC();
     // r = b - c (sum_k Kr_k (x) Mr_others) ubar   (closure -> interior)
     {
@@ -282,7 +303,9 @@ struct PatchBody {
         if (e < nd) a.u[interior_index(e, g0, m)] = uold[k] + d[e];
       }
     } else {
-      for (int e = tid; e < nd; e += NT) a.u[interior_index(e, g0, m)] += d[e];
+      lane_gather<nd, NT, 16, T>(
+          tid, [&](int e) { return a.u[interior_index(e, g0, m)]; },
+          [&](int e, T x) { a.u[interior_index(e, g0, m)] = x + d[e]; });
     }
   }
 
@@ -297,7 +320,7 @@ struct PatchBody {
   PMG_INLINE static void local_only(int tid, int blk, T *lds, const SmoothArgs<T> &a) {
     T *r = lds + off_r;
     const size_t base = (size_t)blk * nd;
-    for (int e = tid; e < nd; e += NT) r[e] = a.r_blocks[base + e];
+    lane_gather<nd, NT, 16, T>(tid, [&](int e) { return a.r_blocks[base + e]; }, [&](int e, T x) { r[e] = x; });
     PMG_SYNC();
     local_solve(tid, lds, a);
     const T *d = lds + off_d;
@@ -347,27 +370,82 @@ struct ApplyBody {
     // (read by stage 2 only), the input tile in 2D (read by stage 1 only)
     T *in = lds, *ab = lds + R0, *outl = DIM == 3 ? lds + R0 : lds;
     const T *__restrict__ u = a.u;
-    for (int e = tid; e < NId; e += NT) {
-      const int i = e % NI, j = (e / NI) % NI, k = DIM == 3 ? e / (NI * NI) : 0;
-      const int gx = lo[0] + i, gy = lo[1] + j, gz = DIM == 3 ? lo[2] + k : 0;
-      bool ok = gx > 0 && gx < m - 1 && gy > 0 && gy < m - 1;
-      if (DIM == 3) ok = ok && gz > 0 && gz < m - 1;
-      in[e] = ok ? u[gx + m * (gy + m * gz)] : T(0);
+    // owned outputs: bx x by x bz nodes from P*c0 (one more per direction at the upper end)
+    const int bx = hi[0] - P * c0[0], by = hi[1] - P * c0[1], bz = DIM == 3 ? hi[2] - P * c0[2] : 1;
+    const int tot = bx * by * bz;
+    auto out_index = [&](int e, bool &bnd) {
+      const int ox = e % bx, oy = (e / bx) % by, oz = DIM == 3 ? e / (bx * by) : 0;
+      const int gx = P * c0[0] + ox, gy = P * c0[1] + oy, gz = DIM == 3 ? P * c0[2] + oz : 0;
+      bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
+      if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
+      return gx + m * (gy + m * gz);
+    };
+    // b and the boundary values of u at the owned outputs are read up front, with the input
+    // tile, when they fit a few registers per lane; otherwise in groups at the end
+    constexpr int NOm = ipow(NO + 1, DIM), RO = (NOm + NT - 1) / NT;
+    constexpr bool PRE = RO <= 8;
+    T ub[PRE ? RO : 1], bb[PRE ? RO : 1];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int k = 0; k < RO; ++k) {
+        const int e = tid + k * NT;
+        bool bnd;
+        const int gi = out_index(e < tot ? e : tot - 1, bnd);
+        ub[k] = u[gi];
+        if (RESID) bb[k] = a.b[gi];
+      }
     }
+    // input tile: nodes outside the mesh or on its boundary are zero (the load address is
+    // clamped into the mesh and the value dropped)
+    lane_gather<NId, NT, 24, T>(
+        tid,
+        [&](int e) {
+          const int i = e % NI, j = (e / NI) % NI, k = DIM == 3 ? e / (NI * NI) : 0;
+          const int gx = lo[0] + i, gy = lo[1] + j, gz = DIM == 3 ? lo[2] + k : 0;
+          bool ok = gx > 0 && gx < m - 1 && gy > 0 && gy < m - 1;
+          if (DIM == 3) ok = ok && gz > 0 && gz < m - 1;
+          const int cx = gx < 0 ? 0 : (gx > m - 1 ? m - 1 : gx);
+          const int cy = gy < 0 ? 0 : (gy > m - 1 ? m - 1 : gy);
+          const int cz = gz < 0 ? 0 : (gz > m - 1 ? m - 1 : gz);
+          const T x = u[cx + m * (cy + m * cz)];
+          return ok ? x : T(0);
+        },
+        [&](int e, T x) { in[e] = x; });
     PMG_SYNC();
     laplace_sf<DIM, PatTile<P, TC>, NT>(tid, in, outl, (const T *)nullptr, a.c, a.Kt, a.Mt, ab, in);
     PMG_SYNC();
-    const int bx = hi[0] - P * c0[0], by = hi[1] - P * c0[1], bz = DIM == 3 ? hi[2] - P * c0[2] : 1;
-    const int tot = bx * by * bz;
-    for (int e = tid; e < tot; e += NT) {
+    auto finish = [&](int e, T uv, T bv) {
+      bool bnd;
+      const int gi = out_index(e, bnd);
       const int ox = e % bx, oy = (e / bx) % by, oz = DIM == 3 ? e / (bx * by) : 0;
-      const int gx = P * c0[0] + ox, gy = P * c0[1] + oy, gz = DIM == 3 ? P * c0[2] + oz : 0;
-      bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
-      if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
-      const int gi = gx + m * (gy + m * gz);
-      T val = bnd ? u[gi] : outl[ox + NO * (oy + NO * oz)];
-      if (RESID) val = a.b[gi] - val;
+      T val = bnd ? uv : outl[ox + NO * (oy + NO * oz)];
+      if (RESID) val = bv - val;
       a.out[gi] = val;
+    };
+    if constexpr (PRE) {
+#pragma unroll
+      for (int k = 0; k < RO; ++k) {
+        const int e = tid + k * NT;
+        if (e < tot) finish(e, ub[k], RESID ? bb[k] : T(0));
+      }
+    } else {
+      constexpr int G = 8;
+      for (int k0 = 0; k0 < RO; k0 += G) {
+        T uu[G], vb[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          const int e = tid + (k0 + k) * NT;
+          bool bnd;
+          const int gi = out_index(e < tot ? e : tot - 1, bnd);
+          uu[k] = u[gi];
+          vb[k] = RESID ? a.b[gi] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          const int e = tid + (k0 + k) * NT;
+          if (e < tot) finish(e, uu[k], vb[k]);
+        }
+      }
     }
   }
 };

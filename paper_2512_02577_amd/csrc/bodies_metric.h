@@ -100,10 +100,7 @@ PMG_INLINE void contract_sub(int tid, const T *in, T *out, const T *base, const 
     for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::IS];
 #pragma unroll
     for (int o = 0; o < Pat::nout; ++o) {
-      T acc = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * v[i];
+      const T acc = row1<Pat>(Mat, o, v);
       const int oi = obs + o * X::OS;
       out[oi] = base[oi] - acc;
     }
@@ -115,23 +112,37 @@ PMG_INLINE void contract_sub(int tid, const T *in, T *out, const T *base, const 
 template <int DIM, int NQ, int nq, int NT, typename T, typename S>
 PMG_INLINE void flux(int tid, T *gx, T *gy, T *gz, const S *G, int n, const int c0[3]) {
   constexpr int tot = ipow(NQ, DIM), nqd = ipow(nq, DIM), nc = DIM == 3 ? 6 : 3;
-  for (int e = tid; e < tot; e += NT) {
-    const int i = e % NQ, j = (e / NQ) % NQ, k = DIM == 3 ? e / (NQ * NQ) : 0;
-    const long cell = (long)(c0[0] + i / nq) + (long)n * ((c0[1] + j / nq) + (long)n * (DIM == 3 ? c0[2] + k / nq : 0));
-    const int loc = (i % nq) + nq * ((j % nq) + nq * (DIM == 3 ? k % nq : 0));
-    const long gi = (cell * nqd + loc) * nc;
-    const T a = gx[e], b = gy[e];
-    if (DIM == 3) {
-      const T c = gz[e];
-      const T xx = load_s<T>(G, gi), yy = load_s<T>(G, gi + 1), zz = load_s<T>(G, gi + 2);
-      const T xy = load_s<T>(G, gi + 3), xz = load_s<T>(G, gi + 4), yz = load_s<T>(G, gi + 5);
-      gx[e] = xx * a + xy * b + xz * c;
-      gy[e] = xy * a + yy * b + yz * c;
-      gz[e] = xz * a + yz * b + zz * c;
-    } else {
-      const T xx = load_s<T>(G, gi), yy = load_s<T>(G, gi + 1), xy = load_s<T>(G, gi + 2);
-      gx[e] = xx * a + xy * b;
-      gy[e] = xy * a + yy * b;
+  // the metric loads of GF points per lane are issued together (one round trip per group)
+  constexpr int RF = (tot + NT - 1) / NT, GF = RF < 3 ? RF : 3;
+  for (int k0 = 0; k0 < RF; k0 += GF) {
+    T g[GF][nc];
+#pragma unroll
+    for (int k = 0; k < GF; ++k) {
+      int e = tid + (k0 + k) * NT;
+      e = e < tot ? e : tot - 1;
+      const int i = e % NQ, j = (e / NQ) % NQ, l = DIM == 3 ? e / (NQ * NQ) : 0;
+      const long cell = (long)(c0[0] + i / nq) + (long)n * ((c0[1] + j / nq) + (long)n * (DIM == 3 ? c0[2] + l / nq : 0));
+      const int loc = (i % nq) + nq * ((j % nq) + nq * (DIM == 3 ? l % nq : 0));
+      const long gi = (cell * nqd + loc) * nc;
+#pragma unroll
+      for (int c = 0; c < nc; ++c) g[k][c] = load_s<T>(G, gi + c);
+    }
+#pragma unroll
+    for (int k = 0; k < GF; ++k) {
+      const int e = tid + (k0 + k) * NT;
+      if (k0 + k >= RF || e >= tot) continue;
+      const T a = gx[e], b = gy[e];
+      if (DIM == 3) {
+        const T c = gz[e];
+        const T xx = g[k][0], yy = g[k][1], zz = g[k][2], xy = g[k][3], xz = g[k][4], yz = g[k][5];
+        gx[e] = xx * a + xy * b + xz * c;
+        gy[e] = xy * a + yy * b + yz * c;
+        gz[e] = xz * a + yz * b + zz * c;
+      } else {
+        const T xx = g[k][0], yy = g[k][1], xy = g[k][2];
+        gx[e] = xx * a + xy * b;
+        gy[e] = xy * a + yy * b;
+      }
     }
   }
 }
@@ -310,7 +321,8 @@ struct MetricPatchBody {
     } else {
       constexpr int q = qd(l), qc = qd(l - 1), ndq = ndl(l);
       constexpr int t1size = DIM == 3 ? cmax(kron_t1(DIM, nl(l), nl(l - 1)), kron_t1(DIM, nl(l - 1), nl(l))) : 0;
-      for (int e = tid; e < ndq; e += NT) d[e] = load_s<T>(invD, e) * r[e];
+      lane_gather<ndq, NT, 16, T>(
+          tid, [&](int e) { return load_s<T>(invD, e); }, [&](int e, T x) { d[e] = x * r[e]; });
       PMG_SYNC();
       T *res = lds + off_res;
       vmult_residual<l>(tid, lds, a, c0, d, r, res);
@@ -325,7 +337,8 @@ struct MetricPatchBody {
       if (full) {
         vmult_residual<l>(tid, lds, a, c0, d, r, res);
         PMG_SYNC();
-        for (int e = tid; e < ndq; e += NT) d[e] += load_s<T>(invD, e) * res[e];
+        lane_gather<ndq, NT, 16, T>(
+            tid, [&](int e) { return load_s<T>(invD, e); }, [&](int e, T x) { d[e] += x * res[e]; });
         PMG_SYNC();
       }
     }
@@ -362,27 +375,31 @@ struct MetricPatchBody {
     const int m = P * a.n + 1;
     const int g0[3] = {P * (v[0] - 1), P * (v[1] - 1), DIM == 3 ? P * (v[2] - 1) : 0};
     T *ucl = lds + off_ucl, *r = lds + off_r;
-    for (int e = tid; e < Nd; e += NT) {
-      const int i = e % N, j = (e / N) % N, k = DIM == 3 ? e / (N * N) : 0;
-      const int gx = g0[0] + i, gy = g0[1] + j, gz = g0[2] + k;
-      bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
-      if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
-      ucl[e] = bnd ? T(0) : a.u[gx + (long)m * (gy + (long)m * gz)];
-    }
     const int ez = DIM == 3 ? 1 : 0;
-    for (int e = tid; e < nd; e += NT) {
+    auto interior = [&](int e) {
       const int i = e % n, j = (e / n) % n, k = DIM == 3 ? e / (n * n) : 0;
-      r[e] = a.b[(g0[0] + 1 + i) + (long)m * ((g0[1] + 1 + j) + (long)m * (g0[2] + ez + k))];
-    }
+      return (g0[0] + 1 + i) + (long)m * ((g0[1] + 1 + j) + (long)m * (g0[2] + ez + k));
+    };
+    // closure of u (zero on the Dirichlet boundary; every closure node lies inside the
+    // mesh, so the load itself is always valid) and the interior of b, loads batched
+    lane_gather2<Nd, nd, NT, 16, T>(
+        tid,
+        [&](int e) {
+          const int i = e % N, j = (e / N) % N, k = DIM == 3 ? e / (N * N) : 0;
+          const int gx = g0[0] + i, gy = g0[1] + j, gz = g0[2] + k;
+          bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
+          if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
+          const T x = a.u[gx + (long)m * (gy + (long)m * gz)];
+          return bnd ? T(0) : x;
+        },
+        [&](int e, T x) { ucl[e] = x; }, [&](int e) { return a.b[interior(e)]; }, [&](int e, T x) { r[e] = x; });
     PMG_SYNC();
     metric_patch<DIM, P, PatBpc<P>, NT>(tid, ucl, r, r, a.lev[L - 1].qt, a.lev[L - 1].G, a.n, c0, lds + off_scr);
     PMG_SYNC();
     local_solve(tid, lds, a, pidx, c0);
     const T *d = lds + off_d;
-    for (int e = tid; e < nd; e += NT) {
-      const int i = e % n, j = (e / n) % n, k = DIM == 3 ? e / (n * n) : 0;
-      a.u[(g0[0] + 1 + i) + (long)m * ((g0[1] + 1 + j) + (long)m * (g0[2] + ez + k))] += d[e];
-    }
+    lane_gather<nd, NT, 16, T>(
+        tid, [&](int e) { return a.u[interior(e)]; }, [&](int e, T x) { a.u[interior(e)] = x + d[e]; });
   }
 
   PMG_INLINE static void local_only(int tid, int blk, T *lds, const MetricSmoothArgs<T, S> &a) {
@@ -392,7 +409,7 @@ struct MetricPatchBody {
     const int c0[3] = {v[0] - 1, v[1] - 1, DIM == 3 ? v[2] - 1 : 0};
     T *r = lds + off_r;
     const size_t base = (size_t)blk * nd;
-    for (int e = tid; e < nd; e += NT) r[e] = a.r_blocks[base + e];
+    lane_gather<nd, NT, 16, T>(tid, [&](int e) { return a.r_blocks[base + e]; }, [&](int e, T x) { r[e] = x; });
     PMG_SYNC();
     local_solve(tid, lds, a, pidx, c0);
     const T *d = lds + off_d;
@@ -434,13 +451,17 @@ struct MetricApplyBody {
     const int cz = DIM == 3 ? a.first[2] + 2 * (idx / (a.cnt[0] * a.cnt[1])) : 0;
     const int m = P * a.n + 1;
     T *ue = lds, *w1b = ue + kd, *w2b = w1b + w1, *V = w2b + w2, *gx = V + q3, *gy = gx + q3, *gz = gy + q3;
-    for (int e = tid; e < kd; e += NT) {
-      const int i = e % k, j = (e / k) % k, l = DIM == 3 ? e / (k * k) : 0;
-      const int X = P * cx + i, Y = P * cy + j, Z = P * cz + l;
-      bool bnd = X == 0 || X == m - 1 || Y == 0 || Y == m - 1;
-      if (DIM == 3) bnd = bnd || Z == 0 || Z == m - 1;
-      ue[e] = bnd ? T(0) : a.u[X + (long)m * (Y + (long)m * Z)];
-    }
+    lane_gather<kd, NT, 16, T>(
+        tid,
+        [&](int e) {
+          const int i = e % k, j = (e / k) % k, l = DIM == 3 ? e / (k * k) : 0;
+          const int X = P * cx + i, Y = P * cy + j, Z = P * cz + l;
+          bool bnd = X == 0 || X == m - 1 || Y == 0 || Y == m - 1;
+          if (DIM == 3) bnd = bnd || Z == 0 || Z == m - 1;
+          const T x = a.u[X + (long)m * (Y + (long)m * Z)];
+          return bnd ? T(0) : x;
+        },
+        [&](int e, T x) { ue[e] = x; });
     PMG_SYNC();
     using PB = PatDense<nq, k>;
     using PD = PatDense<nq, nq>;
@@ -489,13 +510,26 @@ struct MetricApplyBody {
       contract1<1, k, nq, 1, PBT, NT, false>(tid, w1b, ue, a.qt.BT);
     }
     PMG_SYNC();
-    for (int e = tid; e < kd; e += NT) {
+    // out += sign * (cell result) on the cell's interior-of-mesh nodes (cells of one color
+    // share no node); the loads of out are batched
+    auto node = [&](int e, bool &bnd) {
       const int i = e % k, j = (e / k) % k, l = DIM == 3 ? e / (k * k) : 0;
       const int X = P * cx + i, Y = P * cy + j, Z = P * cz + l;
-      bool bnd = X == 0 || X == m - 1 || Y == 0 || Y == m - 1;
+      bnd = X == 0 || X == m - 1 || Y == 0 || Y == m - 1;
       if (DIM == 3) bnd = bnd || Z == 0 || Z == m - 1;
-      if (!bnd) a.out[X + (long)m * (Y + (long)m * Z)] += a.sign * ue[e];
-    }
+      return X + (long)m * (Y + (long)m * Z);
+    };
+    lane_gather<kd, NT, 16, T>(
+        tid,
+        [&](int e) {
+          bool bnd;
+          return a.out[node(e, bnd)];
+        },
+        [&](int e, T x) {
+          bool bnd;
+          const long gi = node(e, bnd);
+          if (!bnd) a.out[gi] = x + a.sign * ue[e];
+        });
   }
 };
 

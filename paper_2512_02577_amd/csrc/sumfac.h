@@ -44,6 +44,57 @@ PMG_INLINE cptr<T> as_const(const T *p) {
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// ---- gathers from global memory ----------------------------------------------------------
+// Two per-lane strided streams, e = tid, tid + NT, ... < C1 (then < C2), read from global
+// memory and stored (to LDS or registers).  A rolled loop that stores each value right after
+// its load waits for every load in turn; here the loads of up to G slots (both streams
+// together) are issued before the first is consumed, so a lane waits about once per group.
+// ld1/ld2 are called for every slot, with e clamped into range on the lanes past the end,
+// so they must be branch-free loads valid for every e < C (select, do not skip); st1/st2
+// run only for e < C.
+template <int C1, int C2, int NT, int G, typename T, class L1, class S1, class L2, class S2>
+PMG_INLINE void lane_gather2(int tid, L1 &&ld1, S1 &&st1, L2 &&ld2, S2 &&st2) {
+  constexpr int R1 = (C1 + NT - 1) / NT, R2 = (C2 + NT - 1) / NT, R = R1 + R2;
+  constexpr int GG = R < G ? R : G;
+#pragma unroll
+  for (int j0 = 0; j0 < R; j0 += GG) {
+    T v[GG];
+#pragma unroll
+    for (int k = 0; k < GG; ++k) {
+      const int j = j0 + k;
+      if (j < R1) {
+        const int e = tid + j * NT;
+        v[k] = ld1(e < C1 ? e : C1 - 1);
+      } else if (j < R) {
+        const int e = tid + (j - R1) * NT;
+        v[k] = ld2(e < C2 ? e : C2 - 1);
+      }
+    }
+#if defined(__HIP_DEVICE_COMPILE__)
+    // an empty asm that takes every value keeps the compiler from sinking a load into the
+    // conditional store of its slot (which would wait for it there, alone)
+#pragma unroll
+    for (int k = 0; k < GG; ++k) asm volatile("" : "+v"(v[k]));
+#endif
+#pragma unroll
+    for (int k = 0; k < GG; ++k) {
+      const int j = j0 + k;
+      if (j < R1) {
+        const int e = tid + j * NT;
+        if (e < C1) st1(e, v[k]);
+      } else if (j < R) {
+        const int e = tid + (j - R1) * NT;
+        if (e < C2) st2(e, v[k]);
+      }
+    }
+  }
+}
+
+template <int C, int NT, int G, typename T, class L, class S>
+PMG_INLINE void lane_gather(int tid, L &&ld, S &&st) {
+  lane_gather2<C, 0, NT, G, T>(tid, ld, st, [](int) { return T(0); }, [](int, T) {});
+}
+
 // ---- sparsity patterns of the 1D matrices ---------------------------------------------
 // Patch interior matrix of degree Q: rows/cols are the 2Q-1 interior nodes of two cells.
 template <int Q>
@@ -82,6 +133,38 @@ struct PatTile {
   PMG_HD static constexpr int hi(int o) { return P * (o / P + 1) + P + 1; }
 };
 
+// ---- one output of a 1D contraction on a register pencil ------------------------------
+// Row o of a matrix with sparsity Pat as one FMA chain seeded with its first product: an
+// accumulator started at 0 costs one more instruction (0 + x is not folded away under IEEE
+// signed zeros), and "acc += K a + M b" would round K a + M b first (mul, fma, add per
+// term) instead of chaining two FMAs.
+template <class Pat, typename T, class MP>
+PMG_INLINE T row1(const MP &M, int o, const T *v) {
+  const int l = Pat::lo(o), h = Pat::hi(o);
+  if (h <= l) return T(0);
+  T acc = M[o * Pat::nin + l] * v[l];
+#pragma unroll
+  for (int i = 0; i < Pat::nin; ++i)
+    if (i > l && i < h) acc += M[o * Pat::nin + i] * v[i];
+  return acc;
+}
+
+// Row o of K va + M vb (same pattern) as one FMA chain
+template <class Pat, typename T, class MP>
+PMG_INLINE T row2(const MP &K, const MP &M, int o, const T *va, const T *vb) {
+  const int l = Pat::lo(o), h = Pat::hi(o);
+  if (h <= l) return T(0);
+  T acc = K[o * Pat::nin + l] * va[l];
+  acc += M[o * Pat::nin + l] * vb[l];
+#pragma unroll
+  for (int i = 0; i < Pat::nin; ++i)
+    if (i > l && i < h) {
+      acc += K[o * Pat::nin + i] * va[i];
+      acc += M[o * Pat::nin + i] * vb[i];
+    }
+  return acc;
+}
+
 // ---- axis bookkeeping -----------------------------------------------------------------
 template <int AX, int E0, int E1, int E2, int NOUT>
 struct Axis {
@@ -118,15 +201,8 @@ PMG_INLINE void contract2(int tid, const T *in, T *oa, const T *A_, T *ob, const
     for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::IS];
 #pragma unroll
     for (int o = 0; o < Pat::nout; ++o) {
-      T sa = 0, sb = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) {
-          sa += A[o * Pat::nin + i] * v[i];
-          sb += B[o * Pat::nin + i] * v[i];
-        }
-      oa[obs + o * X::OS] = sa;
-      ob[obs + o * X::OS] = sb;
+      oa[obs + o * X::OS] = row1<Pat>(A, o, v);
+      ob[obs + o * X::OS] = row1<Pat>(B, o, v);
     }
   }
 }
@@ -148,16 +224,8 @@ PMG_INLINE void contract_pair(int tid, const T *ia, const T *ib_, T *oc, T *og, 
     }
 #pragma unroll
     for (int o = 0; o < Pat::nout; ++o) {
-      T sc = 0, sg = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) {
-          T m = M[o * Pat::nin + i];
-          sc += m * va[i];
-          sg += K[o * Pat::nin + i] * va[i] + m * vb[i];
-        }
-      oc[obs + o * X::OS] = sc;
-      og[obs + o * X::OS] = sg;
+      oc[obs + o * X::OS] = row1<Pat>(M, o, va);
+      og[obs + o * X::OS] = row2<Pat>(K, M, o, va, vb);
     }
   }
 }
@@ -180,10 +248,7 @@ PMG_INLINE void contract_final(int tid, const T *ia, const T *ib_, T *out, const
     }
 #pragma unroll
     for (int o = 0; o < Pat::nout; ++o) {
-      T acc = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += K[o * Pat::nin + i] * va[i] + M[o * Pat::nin + i] * vb[i];
+      const T acc = row2<Pat>(K, M, o, va, vb);
       const int oi = obs + o * X::OS;
       out[oi] = base ? base[oi] - s * acc : s * acc;
     }
@@ -204,10 +269,7 @@ PMG_INLINE void contract1(int tid, const T *in, T *out, const T *Mat_) {
     for (int i = 0; i < Pat::nin; ++i) v[i] = in[ib + i * X::IS];
 #pragma unroll
     for (int o = 0; o < Pat::nout; ++o) {
-      T acc = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * v[i];
+      const T acc = row1<Pat>(Mat, o, v);
       const int oi = obs + o * X::OS;
       if (ADD)
         out[oi] += acc;
@@ -327,7 +389,14 @@ struct WSplit {
         f.template store<0, NOUT>(pen, r);
       }
     } else {
-      const int part = tid / (64 * PW), pen = tid % (64 * PW);
+      // part is the same on every lane of a wave (64 PW lanes per part); saying so makes
+      // the part branches scalar, so each keeps its matrix entries as scalar operands
+#if defined(__HIP_DEVICE_COMPILE__)
+      const int part = __builtin_amdgcn_readfirstlane(tid / (64 * PW));
+#else
+      const int part = tid / (64 * PW);
+#endif
+      const int pen = tid % (64 * PW);
       const bool act = part < parts && pen < NPEN;
       if (act) f.load(pen, r);
       if constexpr (INPL) PMG_SYNC();
@@ -366,15 +435,8 @@ struct FC2 {  // oa = A in, ob = B in
     const int oab = X::template base<LA>(pen), obb = X::template base<LB>(pen);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      T sa = 0, sb = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) {
-          sa += A[o * Pat::nin + i] * r.v[i];
-          sb += B[o * Pat::nin + i] * r.v[i];
-        }
-      oa[oab + o * X::template step<LA>()] = sa;
-      ob[obb + o * X::template step<LB>()] = sb;
+      oa[oab + o * X::template step<LA>()] = row1<Pat>(A, o, r.v);
+      ob[obb + o * X::template step<LB>()] = row1<Pat>(B, o, r.v);
     }
   }
 };
@@ -400,16 +462,8 @@ struct FCPair {  // ia <- M ia, ib <- K ia + M ib
     const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      T sc = 0, sg = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) {
-          const T m = M[o * Pat::nin + i];
-          sc += m * r.va[i];
-          sg += K[o * Pat::nin + i] * r.va[i] + m * r.vb[i];
-        }
-      ia[ab + o * X::template step<LA>()] = sc;
-      ib[bb + o * X::template step<LB>()] = sg;
+      ia[ab + o * X::template step<LA>()] = row1<Pat>(M, o, r.va);
+      ib[bb + o * X::template step<LB>()] = row2<Pat>(K, M, o, r.va, r.vb);
     }
   }
 };
@@ -438,10 +492,7 @@ struct FCFinal {  // out = base - s (K ia + M ib)
     const int ob = X::template base<LO>(pen);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      T acc = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += K[o * Pat::nin + i] * r.va[i] + M[o * Pat::nin + i] * r.vb[i];
+      const T acc = row2<Pat>(K, M, o, r.va, r.vb);
       const int oi = ob + o * X::template step<LO>();
       out[oi] = base[oi] - s * acc;
     }
@@ -467,10 +518,7 @@ struct FC1 {  // out (=|+=) Mat in
     const int ob = X::template base<LO>(pen);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      T acc = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * r.v[i];
+      const T acc = row1<Pat>(Mat, o, r.v);
       const int oi = ob + o * X::template step<LO>();
       if (ADD)
         out[oi] += acc;
@@ -536,10 +584,7 @@ struct FCSub {  // out = base - Mat in
     const int ob = X::template base<LO>(pen);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      T acc = 0;
-#pragma unroll
-      for (int i = 0; i < Pat::nin; ++i)
-        if (i >= Pat::lo(o) && i < Pat::hi(o)) acc += Mat[o * Pat::nin + i] * r.v[i];
+      const T acc = row1<Pat>(Mat, o, r.v);
       const int oi = ob + o * X::template step<LO>();
       out[oi] = base[oi] - acc;
     }
