@@ -24,6 +24,27 @@ __device__ inline int seg_of(const cptr<Stage> &st, int nseg, long item) {
   return s;
 }
 
+// The bodies read the arguments of a work item through a reference to its stage-table entry
+// in the constant address space, field by field as they need them (scalar loads, as for kernel
+// arguments); a local copy of the whole struct would hold every field in registers throughout
+// the body.
+template <typename A>
+__device__ inline const A &table_ref(const PMG_CONST_AS A &x) {
+  return *(const A *)&x;
+}
+
+// The lane index as a value the compiler cannot see through, taken anew in every iteration of
+// a persistent loop: otherwise every index computation of the body that depends on the lane
+// alone is hoisted out of the loop and held in registers across the whole body (more than
+// twice the registers of the single-launch kernel, and lower occupancy).
+template <int NT>
+__device__ inline int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  __builtin_assume(t >= 0 && t < NT);  // the range the loops of the body rely on
+  return t;
+}
+
 // One kernel per degree: the patch body of the single-problem kernel (same threads per
 // workgroup, same registers) inside a loop over the work items of every segment.
 template <typename T, int P>
@@ -37,9 +58,7 @@ __global__ __launch_bounds__(patch_threads(P)) void k_bsmooth(const BSmoothStage
     if (!as_const(st->active)[st->seg[s].prob]) continue;
     const int local = blk - st->seg[s].start;
     if (local >= st->seg[s].a.n_patch) continue;  // padding of the segment to a multiple of 8
-    SmoothArgs<T> a;
-    a = st->seg[s].a;
-    B::smooth_patch(threadIdx.x, local, lds, a);
+    B::smooth_patch(opaque_tid<patch_threads(P)>(), local, lds, table_ref(st->seg[s].a));
     __syncthreads();
   }
 }
@@ -55,9 +74,7 @@ __global__ __launch_bounds__(apply_threads(P)) void k_bapply(const BApplyStage<T
     if (!as_const(st->active)[st->seg[s].prob]) continue;
     const int local = blk - st->seg[s].start;
     if (local >= st->seg[s].a.n_tiles) continue;  // padding of the segment to a multiple of 8
-    ApplyArgs<T> a;
-    a = st->seg[s].a;
-    B::run(threadIdx.x, local, lds, a);
+    B::run(opaque_tid<apply_threads(P)>(), local, lds, table_ref(st->seg[s].a));
     __syncthreads();
   }
 }
@@ -82,8 +99,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_bpass(const BPassStage<T> *st
     const int s = seg_of(st, nseg, g0);
     const long local = g0 - st->seg[s].start + threadIdx.x;
     if (local >= st->seg[s].total || !as_const(st->active)[st->seg[s].prob]) continue;
-    PassArgs<T> pa;
-    pa = st->seg[s].pa;
+    const PassArgs<T> &pa = table_ref(st->seg[s].pa);
     const int mode = st->seg[s].mode;
     switch (st->seg[s].p) {
       case 1: pass_item<T, 1>(mode, local, pa); break;
@@ -103,9 +119,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_bcoarse(const BCoarseStage<T> *st_) {
   const cptr<BCoarseStage<T>> st = as_const(st_);
   if (!as_const(st->active)[st->prob[blockIdx.x]]) return;
-  CoarseArgs<T> a;
-  a = st->seg[blockIdx.x];
-  CoarseBody<3, T, 256>::run(threadIdx.x, a);
+  CoarseBody<3, T, 256>::run(threadIdx.x, table_ref(st->seg[blockIdx.x]));
 }
 
 // kind 0: z = 0 on interior nodes, z = r on boundary nodes (in = r, out = z, type T)

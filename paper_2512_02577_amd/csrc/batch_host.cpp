@@ -44,7 +44,10 @@ struct Step {
 // Launch parameters of one plan: persistent workgroups per compute unit of each kernel
 // (0: one workgroup per work item) and the apply tile option, per degree.
 struct Tuning {
-  int lanes = 1;  // 1: the launches of one stage run as parallel branches, 0: one after another
+  // the launches of one stage (one per degree) run as parallel branches when the stage has at
+  // most this many work items in all, else one after another: a launch that fills the GPU by
+  // itself only competes for compute units and caches with the ones beside it
+  int lane_items = 4096;
   int smooth_wpc[kMaxDegree + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   int apply_wpc[kMaxDegree + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   int pass_wpc = 0, elem_wpc = 0;
@@ -497,7 +500,9 @@ int run_steps(pmg_batch *bt, const Plan<T> &pl, hipStream_t st, const std::funct
       if (!keep || keep(v[j])) grp.push_back(&v[j]);
       ++j;
     }
-    if (grp.size() == 1 || !pl.tune.lanes) {
+    long items = 0;
+    for (const Step *g : grp) items += g->items;
+    if (grp.size() == 1 || items > pl.tune.lane_items) {
       for (const Step *g : grp) PMG_TRY(launch_step(pl, *g, st));
     } else {
       PMG_HIP(hipEventRecord(bt->ev_fork, st));
@@ -590,7 +595,7 @@ std::vector<Knob> knobs(pmg_batch *bt, Plan<T> &pl, bool outer) {
   bool deg[kMaxDegree + 1] = {};
   for (pmg_problem *pr : bt->pr) deg[pr->p] = true;
   const std::vector<int> wpc = {0, 1, 2, 4, 8};
-  k.push_back({"lanes", &pl.tune.lanes, {1, 0}, nullptr, false});
+  k.push_back({"lane_items", &pl.tune.lane_items, {0, 1024, 4096, 16384, 1 << 30}, nullptr, false});
   for (int p = 1; p <= kMaxDegree; ++p) {
     if (!deg[p]) continue;
     const std::string d = "/p" + std::to_string(p);

@@ -191,7 +191,7 @@ def test_tuning_cache_written_and_reused(tmp_path):
     data = json.load(open(path))
     keys = set(data)
     assert any(k.endswith("fp32/smooth_wpc/p2") for k in keys) and any("fp64-outer/apply_wpc/p5" in k for k in keys)
-    assert any(k.endswith("fp32/apply_tile/p5") for k in keys) and any(k.endswith("fp32/lanes") for k in keys)
+    assert any(k.endswith("fp32/apply_tile/p5") for k in keys) and any(k.endswith("fp32/lane_items") for k in keys)
     assert not any("/fp64/" in k for k in keys)
     assert all(v in (0, 1, 2, 4, 8, 16) for v in data.values())
     before = os.stat(path).st_mtime_ns
