@@ -369,6 +369,10 @@ struct ApplyBody {
     // the output tile overlays whatever is dead when the last stage writes it: ab in 3D
     // (read by stage 2 only), the input tile in 2D (read by stage 1 only)
     T *in = lds, *ab = lds + R0, *outl = DIM == 3 ? lds + R0 : lds;
+    if constexpr (DIM == 3) {
+      run3(tid, a, m, c0, lo, hi, in, ab, outl);
+      return;
+    }
     const T *__restrict__ u = a.u;
     // owned outputs: bx x by x bz nodes from P*c0 (one more per direction at the upper end)
     const int bx = hi[0] - P * c0[0], by = hi[1] - P * c0[1], bz = DIM == 3 ? hi[2] - P * c0[2] : 1;
@@ -445,6 +449,123 @@ struct ApplyBody {
           const int e = tid + (k0 + k) * NT;
           if (e < tot) finish(e, uu[k], vb[k]);
         }
+      }
+    }
+  }
+
+  // 3D: the tile is read and written as columns along z.  Each lane owns columns (i, j) and
+  // walks k with a running address, so the index arithmetic is done once per column and the
+  // per-plane tests (the same on every lane) are scalar.
+  PMG_INLINE static void run3(int tid, const ApplyArgs<T> &a, int m, const int c0[3], const int lo[3],
+                              const int hi[3], T *in, T *ab, T *outl) {
+    const T *__restrict__ u = a.u;
+    const int m2 = m * m;
+    constexpr int LP = NT < 64 ? NT : 64, NW = NT / LP;  // lanes per wave, waves
+    constexpr int NO1 = NO + 1;
+    // ---- owned outputs: columns (ox, oy) of bx x by, LP per pass; each wave a range of oz
+    const int bx = hi[0] - P * c0[0], by = hi[1] - P * c0[1], bz = hi[2] - P * c0[2];
+    const int bxy = bx * by;
+    constexpr int QC = (NO1 * NO1 + LP - 1) / LP, ZS = (NO1 + NW - 1) / NW;
+    const int lane = tid % LP, w = tid / LP;
+    const int zs = (bz + NW - 1) / NW, z0 = w * zs;
+    int gcol[QC], lcol[QC];
+    bool bxyc[QC];
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      int e2 = lane + LP * q;
+      e2 = e2 < bxy ? e2 : bxy - 1;
+      const int ox = e2 % bx, oy = e2 / bx;
+      const int gx = P * c0[0] + ox, gy = P * c0[1] + oy;
+      bxyc[q] = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
+      gcol[q] = gx + m * gy;
+      lcol[q] = ox + NO * oy;
+    }
+    auto zidx = [&](int z) {  // owned plane of slot z (clamped)
+      const int oz = z0 + z;
+      return oz < bz ? oz : bz - 1;
+    };
+    // ---- input tile: NI^2 columns of NI nodes; nodes outside the mesh or on its boundary are
+    // zero (the load address is clamped into the mesh and the value dropped).  QG columns per
+    // lane are in flight together.
+    constexpr int NC = NI * NI, QI = (NC + NT - 1) / NT, QG = NI * 2 <= 32 ? 2 : 1;
+#pragma unroll
+    for (int q0 = 0; q0 < QI; q0 += QG) {
+      T v[QG][NI];
+      int e2s[QG];
+#pragma unroll
+      for (int g = 0; g < QG; ++g) {
+        int e2 = tid + (q0 + g) * NT;
+        e2s[g] = e2;
+        e2 = e2 < NC ? e2 : NC - 1;
+        const int i = e2 % NI, j = e2 / NI;
+        const int gx = lo[0] + i, gy = lo[1] + j;
+        const bool okxy = gx > 0 && gx < m - 1 && gy > 0 && gy < m - 1;
+        const int cx = gx < 0 ? 0 : (gx > m - 1 ? m - 1 : gx);
+        const int cy = gy < 0 ? 0 : (gy > m - 1 ? m - 1 : gy);
+        const T *col = u + (cx + m * cy);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+          const int gz = lo[2] + k;
+          const bool ok = okxy && gz > 0 && gz < m - 1;
+          const int cz = gz < 0 ? 0 : (gz > m - 1 ? m - 1 : gz);
+          const T x = col[m2 * cz];
+          v[g][k] = ok ? x : T(0);
+        }
+      }
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+      for (int g = 0; g < QG; ++g)
+#pragma unroll
+        for (int k = 0; k < NI; ++k) asm volatile("" : "+v"(v[g][k]));
+#endif
+#pragma unroll
+      for (int g = 0; g < QG; ++g)
+        if (q0 + g < QI && e2s[g] < NC) {
+#pragma unroll
+          for (int k = 0; k < NI; ++k) in[e2s[g] + NC * k] = v[g][k];
+        }
+    }
+    PMG_SYNC();
+    // the three stages of the tile operator (as laplace_sf: A = Mx u, B = Kx u; C = My A,
+    // G = Ky A + My B in the dead input tile; out = c (Kz C + Mz G))
+    using Pat = PatTile<P, TC>;
+    constexpr int SA = NO * NI * NI, SC = NO * NO * NI;
+    contract2<0, NI, NI, NI, Pat, NT>(tid, in, ab, a.Mt, ab + SA, a.Kt);
+    PMG_SYNC();
+    contract_pair<1, NO, NI, NI, Pat, NT>(tid, ab, ab + SA, in, in + SC, a.Mt, a.Kt);
+    PMG_SYNC();
+    // b, and u where an owned node is on the mesh boundary (only tiles at the mesh faces have
+    // such nodes), are read here so that their loads overlap the last stage, where the
+    // fewest registers are live
+    const bool edge = c0[0] == 0 || c0[1] == 0 || c0[2] == 0 || hi[0] == m || hi[1] == m || hi[2] == m;
+    T bb[RESID ? QC : 1][RESID ? ZS : 1], ub[QC][ZS];
+    if constexpr (RESID) {
+#pragma unroll
+      for (int q = 0; q < QC; ++q)
+#pragma unroll
+        for (int z = 0; z < ZS; ++z) bb[q][z] = a.b[gcol[q] + m2 * (P * c0[2] + zidx(z))];
+    }
+    if (edge) {
+#pragma unroll
+      for (int q = 0; q < QC; ++q)
+#pragma unroll
+        for (int z = 0; z < ZS; ++z) ub[q][z] = u[gcol[q] + m2 * (P * c0[2] + zidx(z))];
+    }
+    contract_final<2, NO, NO, NI, Pat, NT>(tid, in, in + SC, outl, (const T *)nullptr, a.c, a.Kt, a.Mt);
+    PMG_SYNC();
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      if (lane + LP * q >= bxy) continue;
+#pragma unroll
+      for (int z = 0; z < ZS; ++z) {
+        const int oz = z0 + z;
+        if (z >= zs || oz >= bz) continue;
+        const int gz = P * c0[2] + oz;
+        const bool bnd = bxyc[q] || gz == 0 || gz == m - 1;
+        T val = outl[lcol[q] + NO * NO * oz];
+        if (edge && bnd) val = ub[q][z];
+        if constexpr (RESID) val = bb[q][z] - val;
+        a.out[gcol[q] + m2 * gz] = val;
       }
     }
   }

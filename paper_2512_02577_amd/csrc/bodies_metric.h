@@ -91,8 +91,9 @@ template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
 PMG_INLINE void contract_sub(int tid, const T *in, T *out, const T *base, const T *Mat_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
   static_assert(X::NIN == Pat::nin, "extent mismatch");
-  const cptr<T> Mat = as_const(Mat_);
+  const cptr<T> Mat0 = as_const(Mat_);
   for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const cptr<T> Mat = per_pencil(Mat0);
     int ib, obs;
     X::base(pen, ib, obs);
     T v[Pat::nin];

@@ -41,6 +41,25 @@ PMG_INLINE cptr<T> as_const(const T *p) {
   return (cptr<T>)p;
 }
 
+// The same table pointer, as a value the compiler cannot carry over from an earlier pencil
+// of the same loop: the matrix entries of each pencil are then loaded where they are used
+// (scalar-cache hits) instead of being hoisted out of the pencil loop, where the entries
+// of a 1D matrix outnumber the scalar registers and spill into vector-register lanes.
+template <typename T>
+PMG_INLINE cptr<T> per_pencil(cptr<T> p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // the tables are the same on every lane: read the address from the first lane (a no-op
+  // where it is already scalar) and pass it through an empty scalar asm operand
+  const unsigned long long v = (unsigned long long)p;
+  unsigned long long w = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(v >> 32)) << 32) |
+                         (unsigned)__builtin_amdgcn_readfirstlane((unsigned)v);
+  asm volatile("" : "+s"(w));
+  return (cptr<T>)w;
+#else
+  return p;
+#endif
+}
+
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
@@ -191,9 +210,10 @@ struct Axis {
 template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
 PMG_INLINE void contract2(int tid, const T *in, T *oa, const T *A_, T *ob, const T *B_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
-  const cptr<T> A = as_const(A_), B = as_const(B_);
+  const cptr<T> A0 = as_const(A_), B0 = as_const(B_);
   static_assert(X::NIN == Pat::nin, "extent mismatch");
   for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const cptr<T> A = per_pencil(A0), B = per_pencil(B0);
     int ib, obs;
     X::base(pen, ib, obs);
     T v[Pat::nin];
@@ -211,9 +231,10 @@ PMG_INLINE void contract2(int tid, const T *in, T *oa, const T *A_, T *ob, const
 template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
 PMG_INLINE void contract_pair(int tid, const T *ia, const T *ib_, T *oc, T *og, const T *M_, const T *K_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
-  const cptr<T> M = as_const(M_), K = as_const(K_);
+  const cptr<T> M0 = as_const(M_), K0 = as_const(K_);
   static_assert(X::NIN == Pat::nin, "extent mismatch");
   for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const cptr<T> M = per_pencil(M0), K = per_pencil(K0);
     int ib, obs;
     X::base(pen, ib, obs);
     T va[Pat::nin], vb[Pat::nin];
@@ -235,9 +256,10 @@ template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
 PMG_INLINE void contract_final(int tid, const T *ia, const T *ib_, T *out, const T *base, T s, const T *K_,
                                const T *M_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
-  const cptr<T> K = as_const(K_), M = as_const(M_);
+  const cptr<T> K0 = as_const(K_), M0 = as_const(M_);
   static_assert(X::NIN == Pat::nin, "extent mismatch");
   for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const cptr<T> K = per_pencil(K0), M = per_pencil(M0);
     int ib, obs;
     X::base(pen, ib, obs);
     T va[Pat::nin], vb[Pat::nin];
@@ -259,9 +281,10 @@ PMG_INLINE void contract_final(int tid, const T *ia, const T *ib_, T *out, const
 template <int AX, int E0, int E1, int E2, class Pat, int NT, bool ADD, typename T>
 PMG_INLINE void contract1(int tid, const T *in, T *out, const T *Mat_) {
   using X = Axis<AX, E0, E1, E2, Pat::nout>;
-  const cptr<T> Mat = as_const(Mat_);
+  const cptr<T> Mat0 = as_const(Mat_);
   static_assert(X::NIN == Pat::nin, "extent mismatch");
   for (int pen = tid; pen < X::NPEN; pen += NT) {
+    const cptr<T> Mat = per_pencil(Mat0);
     int ib, obs;
     X::base(pen, ib, obs);
     T v[Pat::nin];
@@ -433,10 +456,11 @@ struct FC2 {  // oa = A in, ob = B in
   template <int O0, int O1>
   PMG_INLINE void store(int pen, const Regs &r) const {
     const int oab = X::template base<LA>(pen), obb = X::template base<LB>(pen);
+    const cptr<T> Ap = per_pencil(A), Bp = per_pencil(B);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      oa[oab + o * X::template step<LA>()] = row1<Pat>(A, o, r.v);
-      ob[obb + o * X::template step<LB>()] = row1<Pat>(B, o, r.v);
+      oa[oab + o * X::template step<LA>()] = row1<Pat>(Ap, o, r.v);
+      ob[obb + o * X::template step<LB>()] = row1<Pat>(Bp, o, r.v);
     }
   }
 };
@@ -460,10 +484,11 @@ struct FCPair {  // ia <- M ia, ib <- K ia + M ib
   template <int O0, int O1>
   PMG_INLINE void store(int pen, const Regs &r) const {
     const int ab = X::template base<LA>(pen), bb = X::template base<LB>(pen);
+    const cptr<T> Mp = per_pencil(M), Kp = per_pencil(K);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      ia[ab + o * X::template step<LA>()] = row1<Pat>(M, o, r.va);
-      ib[bb + o * X::template step<LB>()] = row2<Pat>(K, M, o, r.va, r.vb);
+      ia[ab + o * X::template step<LA>()] = row1<Pat>(Mp, o, r.va);
+      ib[bb + o * X::template step<LB>()] = row2<Pat>(Kp, Mp, o, r.va, r.vb);
     }
   }
 };
@@ -490,9 +515,10 @@ struct FCFinal {  // out = base - s (K ia + M ib)
   template <int O0, int O1>
   PMG_INLINE void store(int pen, const Regs &r) const {
     const int ob = X::template base<LO>(pen);
+    const cptr<T> Kp = per_pencil(K), Mp = per_pencil(M);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      const T acc = row2<Pat>(K, M, o, r.va, r.vb);
+      const T acc = row2<Pat>(Kp, Mp, o, r.va, r.vb);
       const int oi = ob + o * X::template step<LO>();
       out[oi] = base[oi] - s * acc;
     }
@@ -516,9 +542,10 @@ struct FC1 {  // out (=|+=) Mat in
   template <int O0, int O1>
   PMG_INLINE void store(int pen, const Regs &r) const {
     const int ob = X::template base<LO>(pen);
+    const cptr<T> Mp = per_pencil(Mat);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      const T acc = row1<Pat>(Mat, o, r.v);
+      const T acc = row1<Pat>(Mp, o, r.v);
       const int oi = ob + o * X::template step<LO>();
       if (ADD)
         out[oi] += acc;
@@ -582,9 +609,10 @@ struct FCSub {  // out = base - Mat in
   template <int O0, int O1>
   PMG_INLINE void store(int pen, const Regs &r) const {
     const int ob = X::template base<LO>(pen);
+    const cptr<T> Mp = per_pencil(Mat);
 #pragma unroll
     for (int o = O0; o < O1; ++o) {
-      const T acc = row1<Pat>(Mat, o, r.v);
+      const T acc = row1<Pat>(Mp, o, r.v);
       const int oi = ob + o * X::template step<LO>();
       out[oi] = base[oi] - acc;
     }
