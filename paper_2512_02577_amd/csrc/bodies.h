@@ -212,9 +212,15 @@ struct PatchBody {
   }
 
   // Alg. 2: d = LocalSolve(r) on the top level (r at off_r, d at off_d).  Later Richardson
-  // steps keep a running residual r <- r - A c, equal to r_0 - A d.
+  // steps keep a running residual r <- r - A c, equal to r_0 - A d.  ONE: the local solver is
+  // one half V-cycle (the default), compiled without the code of the other variants.
+  template <bool ONE = false>
   PMG_INLINE static void local_solve(int tid, T *lds, const SmoothArgs<T> &a) {
     T *r = lds + off_r, *d = lds + off_d, *cc = lds + off_cc;
+    if constexpr (ONE) {
+      cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, false);
+      return;
+    }
     const bool full = a.full != 0;
     cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, full);
     for (int it = 1; it < a.n_iter; ++it) {
@@ -236,6 +242,7 @@ struct PatchBody {
   }
 
   // One patch of one color: gather, residual, LocalSolve, scatter (Alg. 1 body).
+  template <bool ONE = false>
   PMG_INLINE static void smooth_patch(int tid, int blk, T *lds, const SmoothArgs<T> &a) {
     const int pidx = xcd_remap(blk, a.n_patch);
     int v[3];
@@ -294,7 +301,7 @@ struct PatchBody {
       }
     }
     PMG_SYNC();
-    local_solve(tid, lds, a);
+    local_solve<ONE>(tid, lds, a);
     const T *d = lds + off_d;
     if constexpr (KEEP) {
 #pragma unroll

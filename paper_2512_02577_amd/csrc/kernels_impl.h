@@ -22,19 +22,20 @@ __device__ inline T *lds_arena() {
 }
 
 // ---- patch smoother: one workgroup per patch of one color ----
-template <int DIM, typename T, int P, class H>
+// ONE: the local solver is one half V-cycle (no post-smoothing, one Richardson step).
+template <int DIM, typename T, int P, class H, bool ONE>
 __global__ __launch_bounds__(patch_threads(P)) void k_smooth(SmoothArgs<T> a) {
   using B = PatchBody<DIM, T, patch_threads(P), P, H>;
-  B::smooth_patch(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+  B::template smooth_patch<ONE>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
 // Latency variant for small launches (few patches per CU, as on coarse h-levels): 256
 // lanes per patch, so that the short contraction stages split their outputs over four
 // waves and each patch finishes sooner.
-template <int DIM, typename T, int P, class H>
+template <int DIM, typename T, int P, class H, bool ONE>
 __global__ __launch_bounds__(256) void k_smooth_w(SmoothArgs<T> a) {
   using B = PatchBody<DIM, T, 256, P, H>;
-  B::smooth_patch(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+  B::template smooth_patch<ONE>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
 template <int DIM, typename T, int P, class H>
@@ -126,11 +127,17 @@ struct SmoothL {
       static int run(const SmoothArgs<T> &a, const Arena &ar, hipStream_t s) {
         using B = PatchBody<DIM, T, patch_threads(P), P, H>;
         const size_t bytes = B::arena(a.n_iter) * sizeof(T);
+        const bool one = a.full == 0 && a.n_iter == 1;
         if constexpr (patch_threads(P) < 256)
           if (a.n_patch <= kWideLaunch * ar.ncu && bytes <= ar.lds_max)
-            return launch_arena(k_smooth_w<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256, bytes, ar, s, a);
-        return launch_arena(k_smooth<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, patch_threads(P), bytes, ar,
-                            s, a);
+            return one ? launch_arena(k_smooth_w<DIM, T, P, H, true>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256,
+                                      bytes, ar, s, a)
+                       : launch_arena(k_smooth_w<DIM, T, P, H, false>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256,
+                                      bytes, ar, s, a);
+        return one ? launch_arena(k_smooth<DIM, T, P, H, true>, k_smooth_g<DIM, T, P, H>, a.n_patch,
+                                  patch_threads(P), bytes, ar, s, a)
+                   : launch_arena(k_smooth<DIM, T, P, H, false>, k_smooth_g<DIM, T, P, H>, a.n_patch,
+                                  patch_threads(P), bytes, ar, s, a);
       }
     };
   };
