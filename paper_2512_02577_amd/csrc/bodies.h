@@ -623,27 +623,42 @@ struct TransferPass {
     const long st = istr[ax];
     const cptr<T> W1 = as_const(a.W1), Wr = as_const(a.Wr);
     const int K = o[ax];
+    // every tap is loaded (a fixed, unrolled count, the address clamped into range and the
+    // weight of a missing tap zero), so that the loads of one output are in flight together
     T acc = 0;
     if (RESTRICT) {
       const int mc = P * a.nc + 1;
-      if (K > 0 && K < mc - 1) {  // coarse boundary rows vanish
-        const int cc = K / P, cl = K % P;
-        const int first = cl != 0 ? 2 * P * cc + 1 : 2 * P * (cc - 1) + 1;
-        const int cnt = cl != 0 ? 2 * P - 1 : 4 * P - 1;
-        const int nw = 4 * P - 1;
-        for (int t = 0; t < cnt; ++t) acc += Wr[cl * nw + t] * a.in[base + (long)(first + t) * st];
+      const bool inner = K > 0 && K < mc - 1;  // coarse boundary rows vanish
+      const int cc = K / P, cl = K % P;
+      const int cnt = cl != 0 ? 2 * P - 1 : 4 * P - 1;
+      int first = cl != 0 ? 2 * P * cc + 1 : 2 * P * (cc - 1) + 1;
+      first = inner ? first : 1;
+      constexpr int nw = 4 * P - 1;
+      T x[nw];
+#pragma unroll
+      for (int t = 0; t < nw; ++t) {
+        const T v = a.in[base + (long)(t < cnt ? first + t : first) * st];
+        x[t] = t < cnt ? v : T(0);
       }
+#pragma unroll
+      for (int t = 0; t < nw; ++t) acc += Wr[cl * nw + t] * x[t];
+      acc = inner ? acc : T(0);
     } else {
       const int mf = 2 * P * a.nc + 1, mc = P * a.nc + 1;
-      if (K > 0 && K < mf - 1) {  // fine boundary rows vanish
-        int cc = K / (2 * P);
-        if (cc > a.nc - 1) cc = a.nc - 1;
-        const int al = K - 2 * P * cc;
-        for (int c = 0; c <= P; ++c) {
-          const int Kc = P * cc + c;
-          if (Kc > 0 && Kc < mc - 1) acc += W1[al * (P + 1) + c] * a.in[base + (long)Kc * st];
-        }
+      const bool inner = K > 0 && K < mf - 1;  // fine boundary rows vanish
+      int cc = K / (2 * P);
+      if (cc > a.nc - 1) cc = a.nc - 1;
+      const int al = K - 2 * P * cc;
+      T x[P + 1];
+#pragma unroll
+      for (int c = 0; c <= P; ++c) {
+        const int Kc = P * cc + c;
+        const T v = a.in[base + (long)Kc * st];
+        x[c] = Kc > 0 && Kc < mc - 1 ? v : T(0);
       }
+#pragma unroll
+      for (int c = 0; c <= P; ++c) acc += W1[al * (P + 1) + c] * x[c];
+      acc = inner ? acc : T(0);
     }
     if (ADD)
       a.out[g] += acc;
