@@ -336,7 +336,7 @@ def main():
         roof = {"bound": "alu", "achieved": round(ach_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach_tf / FP64_PEAK_TFLOPS, 4)}
     traffic = measured_traffic()
-    roof.update({"traffic": traffic, "kernel": "k_smooth<3,double,4,{1,3,4}> (finest level, one color launch)",
+    roof.update({"traffic": traffic, "kernel": "k_smooth<3,double,4,{1,3,4},ONE> (finest level, one color launch)",
                  "avg_launch_us": round(t_launch * 1e6, 2), "bytes_per_launch": bytes_launches // ncol,
                  "flops_per_launch": flops // ncol, "flop_per_byte": round(ai, 2),
                  "achieved_tflops": round(ach_tf, 3), "achieved_gbs": round(ach_gbs, 1)})

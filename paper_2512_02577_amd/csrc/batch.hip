@@ -116,10 +116,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_bpass(const BPassStage<T> *st
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_bcoarse(const BCoarseStage<T> *st_) {
+__global__ __launch_bounds__(kCoarseThreads) void k_bcoarse(const BCoarseStage<T> *st_, int lds_elems) {
   const cptr<BCoarseStage<T>> st = as_const(st_);
   if (!as_const(st->active)[st->prob[blockIdx.x]]) return;
-  CoarseBody<3, T, 256>::run(threadIdx.x, table_ref(st->seg[blockIdx.x]));
+  CoarseBody<3, T, kCoarseThreads>::run(threadIdx.x, table_ref(st->seg[blockIdx.x]), lds_arena<double>(), lds_elems);
 }
 
 // kind 0: z = 0 on interior nodes, z = r on boundary nodes (in = r, out = z, type T)
@@ -346,7 +346,19 @@ int BatchLaunch<T>::pass(const BPassStage<T> *st, int grid, hipStream_t s) {
 template <typename T>
 int BatchLaunch<T>::coarse(const BCoarseStage<T> *st, int nseg, hipStream_t s) {
   if (nseg <= 0) return 0;
-  hipLaunchKernelGGL(k_bcoarse<T>, dim3(nseg), dim3(256), 0, s, st);
+  // every segment runs on the device's full LDS; one whose work vectors do not fit it uses
+  // its global buffers
+  const size_t bytes = device_lds_limit();
+  if (bytes > 65536) {
+    static thread_local bool raised = false;
+    if (!raised) {
+      if (hipFuncSetAttribute((const void *)k_bcoarse<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+          hipSuccess)
+        return -4;
+      raised = true;
+    }
+  }
+  hipLaunchKernelGGL(k_bcoarse<T>, dim3(nseg), dim3(kCoarseThreads), bytes, s, st, (int)(bytes / sizeof(double)));
   return ok();
 }
 

@@ -717,12 +717,17 @@ struct CoarseBody {
     for (int e = tid; e < tot; e += NT) {
       const int o = (e / st) % m, base = e - o * st;
       double s = 0.0;
+#pragma unroll 4
       for (int i = 0; i < m; ++i) s += (tr ? a.S[i * m + o] : a.S[o * m + i]) * in[base + i * st];
       out[e] = s;
     }
   }
-  PMG_INLINE static void run(int tid, const CoarseArgs<T> &a) {
+  // lds: lds_elems doubles of workgroup memory; when both work vectors fit there the passes
+  // run on it instead of on the global buffers w1, w2
+  PMG_INLINE static void run(int tid, const CoarseArgs<T> &a, double *lds = nullptr, int lds_elems = 0) {
     const int m = a.m, mt = a.mt, tot = DIM == 3 ? m * m * m : m * m;
+    const bool inl = lds != nullptr && 2 * tot <= lds_elems;
+    double *const w1 = inl ? lds : a.w1, *const w2 = inl ? lds + tot : a.w2;
     const int totall = DIM == 3 ? mt * mt * mt : mt * mt;
     for (int e = tid; e < totall; e += NT) {  // boundary rows are identity rows
       const int i = e % mt, j = (e / mt) % mt, k = DIM == 3 ? e / (mt * mt) : 1;
@@ -732,10 +737,10 @@ struct CoarseBody {
     }
     for (int e = tid; e < tot; e += NT) {
       const int i = e % m, j = (e / m) % m, k = DIM == 3 ? e / (m * m) : 0;
-      a.w1[e] = (double)a.r[(i + 1) + mt * ((j + 1) + mt * (k + (DIM == 3 ? 1 : 0)))];
+      w1[e] = (double)a.r[(i + 1) + mt * ((j + 1) + mt * (k + (DIM == 3 ? 1 : 0)))];
     }
     PMG_SYNC();
-    double *x = a.w1, *y = a.w2;
+    double *x = w1, *y = w2;
     for (int ax = 0; ax < DIM; ++ax) {
       axis(tid, a, x, y, ax, true);
       PMG_SYNC();

@@ -89,8 +89,8 @@ __global__ __launch_bounds__(256) void k_transfer(PassArgs<T> a, long total) {
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
-  CoarseBody<DIM, T, 256>::run(threadIdx.x, a);
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse(CoarseArgs<T> a, int lds_elems) {
+  CoarseBody<DIM, T, kCoarseThreads>::run(threadIdx.x, a, lds_arena<double>(), lds_elems);
 }
 
 // Launch the LDS variant with `bytes` of dynamic shared memory, or the global-arena
@@ -250,7 +250,21 @@ int Launchers<DIM, T>::prolong(int p, const TransferArgs<T> &a, hipStream_t s) {
 }
 template <int DIM, typename T>
 int Launchers<DIM, T>::coarse(const CoarseArgs<T> &a, hipStream_t s) {
-  hipLaunchKernelGGL((detail::k_coarse<DIM, T>), dim3(1), dim3(256), 0, s, a);
+  // the two work vectors of the fast diagonalization in workgroup memory when they fit
+  const size_t tot = DIM == 3 ? (size_t)a.m * a.m * a.m : (size_t)a.m * a.m;
+  size_t bytes = 2 * tot * sizeof(double);
+  if (bytes > device_lds_limit()) bytes = 0;
+  if (bytes > 65536) {
+    static thread_local bool raised = false;
+    if (!raised) {
+      if (hipFuncSetAttribute((const void *)detail::k_coarse<DIM, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)device_lds_limit()) != hipSuccess)
+        return -4;
+      raised = true;
+    }
+  }
+  hipLaunchKernelGGL((detail::k_coarse<DIM, T>), dim3(1), dim3(kCoarseThreads), bytes, s, a,
+                     (int)(bytes / sizeof(double)));
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

@@ -20,6 +20,21 @@ struct Arena {
 // Patch launches with at most this many patches per CU use the 256-lane latency variant.
 constexpr int kWideLaunch = 4;
 
+// Threads of the coarse-solve workgroup.
+constexpr int kCoarseThreads = 512;
+
+// Bytes of LDS a workgroup may use on the current device (queried once per process).
+inline size_t device_lds_limit() {
+  static const size_t v = [] {
+    int d = 0, l = 0;
+    if (hipGetDevice(&d) != hipSuccess ||
+        hipDeviceGetAttribute(&l, hipDeviceAttributeMaxSharedMemoryPerBlock, d) != hipSuccess)
+      return (size_t)0;
+    return (size_t)l;
+  }();
+  return v;
+}
+
 // Kernel launchers of one (dimension, precision); instantiated in kernels_<d>d_<prec>.hip.
 template <int DIM, typename T>
 struct Launchers {
