@@ -341,6 +341,14 @@ def main():
                  "flops_per_launch": flops // ncol, "flop_per_byte": round(ai, 2),
                  "achieved_tflops": round(ach_tf, 3), "achieved_gbs": round(ach_gbs, 1)})
 
+    # the operator apply v = A u on the finest level (one launch): reads u, writes v
+    apply_bytes = 16 * N
+    apply_gbs = apply_bytes / (t_apply * 1e-3) / 1e9
+    roof_apply = {"bound": "hbm", "achieved": round(apply_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(apply_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "kernel": "k_apply<3,double,4> (finest level, v = A u, one launch)",
+                  "avg_launch_us": round(t_apply * 1e3, 2), "bytes_per_launch": apply_bytes}
+
     out = {
         "metric": "DoF/s per V-cycle + time-to-1e-8 residual, FP64 vs FP32-MG, one MI355X",
         "value": N * sum(its) / t64,
@@ -368,6 +376,7 @@ def main():
                "vcycle_fp32": t_vc32},
         "smooth_over_apply": t_smooth / t_apply,
         "roofline": roof,
+        "roofline_operator": roof_apply,
     }
     if not args.no_batch:
         log("bench: 16-problem batch (FP32-MG in FP64 CG) and the same solves one by one")

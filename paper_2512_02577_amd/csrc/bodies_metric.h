@@ -345,8 +345,15 @@ struct MetricPatchBody {
     }
   }
 
+  // ONE: the local solver is one half V-cycle (the default), compiled without the code of
+  // the other variants
+  template <bool ONE = false>
   PMG_INLINE static void local_solve(int tid, T *lds, const MetricSmoothArgs<T, S> &a, long pidx, const int c0[3]) {
     T *r = lds + off_r, *d = lds + off_d, *cc = lds + off_cc;
+    if constexpr (ONE) {
+      cycle<L - 1>(tid, lds, a, pidx, c0, r, d, false);
+      return;
+    }
     const bool full = a.full != 0;
     cycle<L - 1>(tid, lds, a, pidx, c0, r, d, full);
     for (int it = 1; it < a.n_iter; ++it) {
@@ -368,6 +375,7 @@ struct MetricPatchBody {
     return (long)(v[0] - 1) + (long)(ncell - 1) * ((v[1] - 1) + (long)(ncell - 1) * (DIM == 3 ? v[2] - 1 : 0));
   }
 
+  template <bool ONE = false>
   PMG_INLINE static void smooth_patch(int tid, int blk, T *lds, const MetricSmoothArgs<T, S> &a) {
     int v[3];
     vertex(xcd_remap(blk, a.n_patch), a, v);
@@ -397,7 +405,7 @@ struct MetricPatchBody {
     PMG_SYNC();
     metric_patch<DIM, P, PatBpc<P>, NT>(tid, ucl, r, r, a.lev[L - 1].qt, a.lev[L - 1].G, a.n, c0, lds + off_scr);
     PMG_SYNC();
-    local_solve(tid, lds, a, pidx, c0);
+    local_solve<ONE>(tid, lds, a, pidx, c0);
     const T *d = lds + off_d;
     lane_gather<nd, NT, 16, T>(
         tid, [&](int e) { return a.u[interior(e)]; }, [&](int e, T x) { a.u[interior(e)] = x + d[e]; });

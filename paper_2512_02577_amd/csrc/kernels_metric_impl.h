@@ -25,10 +25,11 @@ __device__ inline T *lds_arena() {
   return reinterpret_cast<T *>(smem);
 }
 
-template <int DIM, typename T, typename S, int P, class H>
+// ONE: the local solver is one half V-cycle (no post-smoothing, one Richardson step).
+template <int DIM, typename T, typename S, int P, class H, bool ONE>
 __global__ __launch_bounds__(metric_patch_threads(P, sizeof(T))) void k_msmooth(MetricSmoothArgs<T, S> a) {
   using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>;
-  B::smooth_patch(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+  B::template smooth_patch<ONE>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
 template <int DIM, typename T, typename S, int P, class H>
@@ -109,8 +110,12 @@ struct SmoothF {
   struct F {
     static int run(const MetricSmoothArgs<T, S> &a, const Arena &ar, hipStream_t s) {
       using B = MetricPatchBody<DIM, T, S, metric_patch_threads(P, sizeof(T)), P, H>;
-      return launch_arena(k_msmooth<DIM, T, S, P, H>, k_msmooth_g<DIM, T, S, P, H>, a.n_patch,
-                          metric_patch_threads(P, sizeof(T)), B::arena(a.n_iter) * sizeof(T), ar, s, a);
+      const size_t bytes = B::arena(a.n_iter) * sizeof(T);
+      if (a.full == 0 && a.n_iter == 1)
+        return launch_arena(k_msmooth<DIM, T, S, P, H, true>, k_msmooth_g<DIM, T, S, P, H>, a.n_patch,
+                            metric_patch_threads(P, sizeof(T)), bytes, ar, s, a);
+      return launch_arena(k_msmooth<DIM, T, S, P, H, false>, k_msmooth_g<DIM, T, S, P, H>, a.n_patch,
+                          metric_patch_threads(P, sizeof(T)), bytes, ar, s, a);
     }
   };
 };
