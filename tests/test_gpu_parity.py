@@ -264,3 +264,32 @@ def test_full_size_c2_sampled_rows_and_solve():
         r_rows = b[rows] - apply_rows(mesh, p, xh, rows)
         assert abs(r_rows).max() <= 2e-8 * np.linalg.norm(b)
         assert info.iterations < 30
+
+
+@pytest.mark.gpu
+def test_full_size_c2_smoother_and_vcycle_reduce_energy():
+    # 32^3 Q4 at full size, properties that hold at any size: with b = 0 the iterate is the
+    # error, and one smoothing application (Alg. 1, every color) and one V-cycle's error
+    # propagation e - V(A e) must both lower its energy e^T A e (A through the apply, which
+    # the sampled-row test above checks against the oracle)
+    dim, n, p = 3, 32, 4
+    pr = pmg.make_problem(dim, n, p)
+    L = pr.finest
+    e0 = dev(rhs_vector(dim, n, p, 7))  # random interior values, zero on the boundary
+    Ae = torch.empty_like(e0)
+
+    def energy(e):
+        pmg.apply_operator(pr, L, e, Ae)
+        return float(torch.dot(e, Ae))
+
+    E0 = energy(e0)
+    assert E0 > 0.0
+    e = e0.clone()
+    pmg.smooth(pr, L, e, torch.zeros_like(e0), 1)
+    E1 = energy(e)
+    assert 0.0 < E1 < 0.5 * E0
+    pmg.apply_operator(pr, L, e0, Ae)
+    z = torch.empty_like(e0)
+    pmg.vcycle(pr, Ae.clone(), z, pmg.FP64)
+    E2 = energy(e0 - z)
+    assert 0.0 < E2 < 0.1 * E0
