@@ -258,8 +258,9 @@ int do_smooth(pmg_problem *pr, int l, int dir, T *u, const T *b, hipStream_t s, 
 }
 
 template <typename T>
-int do_restrict(pmg_problem *pr, int l, const T *fine, T *coarse, hipStream_t s) {
+int do_restrict(pmg_problem *pr, int l, const T *fine, T *coarse, hipStream_t s, T *zero = nullptr) {
   TransferArgs<T> a{};
+  a.zero = zero;
   a.W1 = pr->pd<T>().tabs.W1;
   a.Wr = pr->pd<T>().tabs.Wr;
   a.nc = pr->sizes[l - 1];
@@ -315,14 +316,15 @@ int do_vcycle(pmg_problem *pr, const T *r, T *z, hipStream_t s, int store = ST_N
     const T *R = l == L ? r : w.r[l];
     T *Z = l == L ? z : w.z[l];
     const int m = pr->p * pr->sizes[l] + 1;
-    PMG_TRY(launch_init_z<T>(pr->dim, m, Z, R, s));
+    // the coarser levels' zero initial guess is written by the restriction into them
+    if (l == L) PMG_TRY(launch_init_z<T>(pr->dim, m, Z, R, s));
     for (int k = 0; k < pr->cfg.n_pre; ++k) {
       int rc = do_smooth<T>(pr, l, +1, Z, R, s, store);
       if (rc) return rc;
     }
     int rc = do_apply<T>(pr, l, true, R, Z, w.t[l], s, store);
     if (rc) return rc;
-    rc = do_restrict<T>(pr, l, w.t[l], w.r[l - 1], s);
+    rc = do_restrict<T>(pr, l, w.t[l], w.r[l - 1], s, l - 1 >= 1 ? w.z[l - 1] : nullptr);
     if (rc) return rc;
   }
   int rc = do_coarse<T>(pr, w.r[0], w.z[0], s);
