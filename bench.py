@@ -255,7 +255,7 @@ def main():
                     help="also the 64^3 degree sweep and the 48^3 Q6 perturbed-mesh problem (minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
 
