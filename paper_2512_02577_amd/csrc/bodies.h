@@ -121,17 +121,66 @@ struct PatchBody {
   }
 
   // Alg. 3 on p-level l: d = V(l, r), zero initial guess.
+  // Inverse diagonals of the top p-level and of p-level 1 read ahead into registers (with the
+  // patch gathers), so that the local solve does not wait for them; only where they fit a
+  // few registers per lane.
+  static constexpr int RPT = (nd + NT - 1) / NT;
+  static constexpr int RP1 = L >= 3 ? (ndl(1) + NT - 1) / NT : 1;
+  static constexpr bool PRE_T = RPT <= 4, PRE_1 = L >= 3 && RP1 <= 2;
+  struct PreD {
+    T top[PRE_T ? RPT : 1];
+    T l1[PRE_1 ? RP1 : 1];
+  };
+
+  PMG_INLINE static void prefetch_diag(int tid, const DevTabs<T> &tb, PreD &pre) {
+    if constexpr (PRE_T) {
+      const cptr<T> iv = as_const(tb.invD[L - 1]);
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int e = tid + j * NT;
+        pre.top[j] = iv[e < nd ? e : nd - 1];
+      }
+    }
+    if constexpr (PRE_1) {
+      constexpr int n1 = ndl(1);
+      const cptr<T> iv = as_const(tb.invD[1]);
+#pragma unroll
+      for (int j = 0; j < RP1; ++j) {
+        const int e = tid + j * NT;
+        pre.l1[j] = iv[e < n1 ? e : n1 - 1];
+      }
+    }
+  }
+
+  // d = cinv D_l^-1 r on p-level l, from the read-ahead diagonal when there is one
+  template <int l>
+  PMG_INLINE static void jacobi(int tid, const DevTabs<T> &tb, T cinv, const T *r, T *d, const PreD *pre) {
+    constexpr int ndq = ndl(l);
+    constexpr bool HAVE = (l == L - 1 && PRE_T) || (l == 1 && PRE_1);
+    if (HAVE && pre) {
+      constexpr int R = (ndq + NT - 1) / NT;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int e = tid + j * NT;
+        const T x = l == L - 1 ? pre->top[j < RPT ? j : 0] : pre->l1[j < RP1 ? j : 0];
+        if (e < ndq) d[e] = cinv * x * r[e];
+      }
+    } else {
+      const cptr<T> invD = as_const(tb.invD[l]);
+      lane_gather<ndq, NT, 16, T>(tid, [&](int e) { return invD[e]; }, [&](int e, T x) { d[e] = cinv * x * r[e]; });
+    }
+  }
+
   template <int l>
   PMG_INLINE static void cycle(int tid, T *lds, const DevTabs<T> &tb, T c, T cinv, const T *r, T *d,
-                               bool full) {
+                               bool full, const PreD *pre = nullptr) {
     if constexpr (l == 0) {
       if (tid == 0) d[0] = cinv * as_const(tb.invD[0])[0] * r[0];  // exact 1x1 solve
       PMG_SYNC();
     } else {
       constexpr int q = qd(l), qc = qd(l - 1), m = nl(l), mc = nl(l - 1), ndq = ndl(l);
       const cptr<T> invD = as_const(tb.invD[l]);
-      lane_gather<ndq, NT, 16, T>(  // pre-smoothing d = cinv D^-1 r
-          tid, [&](int e) { return invD[e]; }, [&](int e, T x) { d[e] = cinv * x * r[e]; });
+      jacobi<l>(tid, tb, cinv, r, d, pre);  // pre-smoothing d = cinv D^-1 r
       // on p-level 1 the weights of the one-node coarsest level are read now, so that their
       // loads overlap the residual below
       constexpr int R1 = l == 1 ? (ndq + NT - 1) / NT : 1;
@@ -187,7 +236,7 @@ struct PatchBody {
           scontract1<1, mc, m, 1, PR, NT, false, D, DC>(tid, res, rc, tb.TpT[l]);
         }
         PMG_SYNC();
-        cycle<l - 1>(tid, lds, tb, c, cinv, rc, dc, full);
+        cycle<l - 1>(tid, lds, tb, c, cinv, rc, dc, full, pre);
         if constexpr (DIM == 3) {  // d += P dc
           scontract1<0, mc, mc, mc, PP, NT, false, DC, Dense<m, mc>>(tid, dc, X0, tb.Tp[l]);
           PMG_SYNC();
@@ -215,10 +264,10 @@ struct PatchBody {
   // steps keep a running residual r <- r - A c, equal to r_0 - A d.  ONE: the local solver is
   // one half V-cycle (the default), compiled without the code of the other variants.
   template <bool ONE = false>
-  PMG_INLINE static void local_solve(int tid, T *lds, const SmoothArgs<T> &a) {
+  PMG_INLINE static void local_solve(int tid, T *lds, const SmoothArgs<T> &a, const PreD *pre = nullptr) {
     T *r = lds + off_r, *d = lds + off_d, *cc = lds + off_cc;
     if constexpr (ONE) {
-      cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, false);
+      cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, false, pre);
       return;
     }
     const bool full = a.full != 0;
@@ -256,6 +305,8 @@ struct PatchBody {
     // The patch interior of u is written only by this patch while its color runs (no
     // other patch of the color has it in its closure), so the values the final update
     // adds to can be read now, with the gathers, instead of after the local solve.
+    PreD pre;
+    if constexpr (ONE) prefetch_diag(tid, a.tb, pre);
     constexpr int NUI = (nd + NT - 1) / NT;
     constexpr bool KEEP = NUI <= 3;
     T uold[KEEP ? NUI : 1];
@@ -301,7 +352,7 @@ struct PatchBody {
       }
     }
     PMG_SYNC();
-    local_solve<ONE>(tid, lds, a);
+    local_solve<ONE>(tid, lds, a, ONE ? &pre : nullptr);
     const T *d = lds + off_d;
     if constexpr (KEEP) {
 #pragma unroll
