@@ -218,8 +218,8 @@ void pmg_destroy_problem(pmg_problem *pr);
  * with the paper's p-hierarchy (Sec. 2.2), any mix of mesh sizes and degrees.  Their
  * V-cycles are aligned by depth below the finest level: each V-cycle stage (one color
  * sweep, the residual, one 1D transfer pass, the coarse solves, ...) of all problems is
- * one persistent launch per degree present (independent launches, run as parallel
- * branches), and the whole cycle, together with the vector updates of the outer
+ * one persistent launch per degree present (independent launches, run as parallel graph
+ * branches when the stage is small), and the whole cycle, together with the vector updates of the outer
  * flexible CG, is captured once as a HIP graph.  The arithmetic of every problem equals that of pmg_vcycle and
  * pmg_solve on it (the same kernel bodies and tables); only the reduction trees of the
  * CG dot products differ.
@@ -232,9 +232,10 @@ void pmg_destroy_problem(pmg_problem *pr);
 typedef struct pmg_batch pmg_batch;
 
 /* Builds the stage tables of both multigrid precisions (PMG_FP64 only where every
- * degree's patch arena fits in LDS, i.e. p <= 7) and allocates the batch state.  Launch
- * parameters, per degree: persistent workgroups per CU of the patch and apply kernels,
- * the apply tile; plus whether the launches of one stage run as parallel graph branches.
+ * degree's patch arena fits in LDS: all degrees up to 8 with one Richardson step) and
+ * allocates the batch state.  Launch parameters, per degree: persistent workgroups per CU
+ * of the patch and apply kernels, the apply tile; plus the number of work items up to which
+ * the launches of one stage run as parallel graph branches.
  * tuning_cache_path: NULL uses built-in defaults; otherwise a JSON object of
  * "arch/3d/precision/knob": value entries is read, and the first batch call in a
  * precision measures the entries it lacks on the device (seconds: whole V-cycles per
