@@ -136,6 +136,15 @@ def quadrature_points(mesh: StructuredMesh, p: int, nq: int | None = None) -> np
     return np.stack([multilinear_map(mesh.cell_corners(c), pts)[0] for c in range(mesh.n_cells())])
 
 
+def cells_of_node_1d(i: int, n: int, p: int) -> list[int]:
+    """Cells (per direction) whose closed interval holds node i of the degree-p line of
+    n cells: cell i // p, and also cell i // p - 1 when the node is a shared cell end."""
+    cs = {min(i // p, n - 1)}
+    if i % p == 0 and i > 0:
+        cs.add(i // p - 1)
+    return sorted(x for x in cs if 0 <= x < n)
+
+
 def apply_rows(mesh: StructuredMesh, p: int, u: np.ndarray, rows: np.ndarray, coef=None) -> np.ndarray:
     """(A u)_i for selected global rows i without assembling A: the sum over the cells
     that contain node i of (element matrix row) . (element values of u), with the
@@ -150,13 +159,7 @@ def apply_rows(mesh: StructuredMesh, p: int, u: np.ndarray, rows: np.ndarray, co
             out[r_i] = u[g]
             continue
         idx = [(g // m**a) % m for a in range(dim)]
-        cands = []
-        for a in range(dim):
-            c = idx[a] // p
-            cs = {min(c, n - 1)}
-            if idx[a] % p == 0 and idx[a] > 0:
-                cs.add(idx[a] // p - 1)
-            cands.append(sorted(x for x in cs if 0 <= x < n))
+        cands = [cells_of_node_1d(idx[a], n, p) for a in range(dim)]
         total = 0.0
         for cell in np.array(np.meshgrid(*cands, indexing="ij")).reshape(dim, -1).T:
             c = int(sum(cell[a] * n**a for a in range(dim)))
