@@ -64,6 +64,12 @@ enum { PMG_FP64 = 0, PMG_FP32 = 1, PMG_FP32_BF16 = 2 };
  * full V-cycle per Richardson step. */
 enum { PMG_LOCAL_HALF_V = 0, PMG_LOCAL_FULL_V = 1 };
 
+/* Lanes per patch of the Cartesian smoother launches: by launch size (a color with at
+ * most 4 patches per compute unit runs 256 lanes per patch, larger colors the per-degree
+ * count: 64 for p <= 2, 128 for p <= 4, 256 above), or always one of the two.  The
+ * arithmetic is the same; the choice only trades latency against occupancy. */
+enum { PMG_LANES_AUTO = 0, PMG_LANES_NARROW = 1, PMG_LANES_WIDE = 2 };
+
 typedef struct {
   int local_solver; /* PMG_LOCAL_HALF_V (default) or PMG_LOCAL_FULL_V                  */
   int n_local_iter; /* Richardson steps of LocalSolve (Alg. 2), >= 1; default 1          */
@@ -73,6 +79,7 @@ typedef struct {
   double rtol;      /* outer stop: |b - A x|_2 <= rtol |b|_2, default 1e-8               */
   int n_omega;      /* 0: library damping; else the number of valid entries in omega     */
   double omega[8];  /* Jacobi damping per p-level, coarsest first (entry 0 is unused)    */
+  int patch_lanes;  /* PMG_LANES_AUTO (default), PMG_LANES_NARROW or PMG_LANES_WIDE      */
 } pmg_config;
 
 typedef struct {
@@ -93,7 +100,9 @@ void pmg_default_config(pmg_config *cfg);
 
 /* Mesh hierarchy M_0 ... M_L of nested structured meshes (Sec. 2).
  *   dim       2 or 3.
- *   n         cells per direction on the finest mesh, 2 <= n <= 1024.
+ *   n_cells   host array of cells per direction on the finest mesh (dim entries are read),
+ *             each in [2, 1024].  The kernels index square and cubic node grids, so the
+ *             entries must be equal (UNSUPPORTED otherwise); n below is that count.
  *   n_hlevels number of h-levels, or 0: halve n while it is even and above 3.
  *   vertices  NULL for the uniform Cartesian unit box.  Otherwise host array of
  *             (n+1)^dim * dim doubles (vertex-major, x fastest) of a distorted mesh (Sec. 4
@@ -103,7 +112,7 @@ void pmg_default_config(pmg_config *cfg);
  *             the metric w mu |det J| J^-1 J^-T is stored per Gauss point and the patch
  *             diagonals per patch.
  * The mesh owns a copy of everything it needs; *out is set on success only. */
-int pmg_setup_mesh(int dim, int n, int n_hlevels, const double *vertices, pmg_mesh **out);
+int pmg_setup_mesh(int dim, const int32_t *n_cells, int n_hlevels, const double *vertices, pmg_mesh **out);
 
 /* Dimension and number of h-levels (either may be NULL); if n_cells is not NULL it
  * receives the cells per direction of each level, coarsest first (host array of

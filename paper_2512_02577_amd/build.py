@@ -3,6 +3,7 @@ bodies, in-tree, next to this file.
 
     python -m paper_2512_02577_amd.build          # both libraries
     python -m paper_2512_02577_amd.build --asan   # also the bounds-checked emulation runner
+    python -m paper_2512_02577_amd.build --tsan   # also the race-checked emulation runner
 
 Every call compiles from scratch; objects go to paper_2512_02577_amd/_build/.
 """
@@ -68,28 +69,39 @@ def build_hip(jobs: int = 8, only: list[str] | None = None) -> str:
     return LIB
 
 
-def build_emulation(asan: bool = False) -> str:
+def build_emulation(asan: bool = False, tsan: bool = False) -> str:
+    """The CPU emulation library of the kernel bodies; with asan/tsan also the checked
+    runner hostemu_check (AddressSanitizer + UndefinedBehaviorSanitizer, or
+    ThreadSanitizer), a plain g++ build of host code only."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [os.path.join(CSRC, "hostemu.cpp"), os.path.join(CSRC, "host_tables.cpp"), os.path.join(CSRC, "geometry.cpp")]
     tmp = EMU + ".tmp"
     _run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I" + CSRC, *srcs, "-o", tmp, "-lpthread"])
     os.replace(tmp, EMU)
+    out = EMU
+    checked = os.path.join(CSRC, "hostemu_check.cpp")
     if asan:
-        exe = os.path.join(BUILD, "hostemu_asan")
+        out = os.path.join(BUILD, "hostemu_asan")
         _run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
-              "-I" + CSRC, os.path.join(CSRC, "hostemu_check.cpp"), *srcs, "-o", exe, "-lpthread"])
-        return exe
-    return EMU
+              "-I" + CSRC, checked, *srcs, "-o", out, "-lpthread"])
+    if tsan:
+        out = os.path.join(BUILD, "hostemu_tsan")
+        _run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=thread", "-I" + CSRC, checked, *srcs, "-o", out,
+              "-lpthread"])
+    return out
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--asan", action="store_true")
+    ap.add_argument("--tsan", action="store_true")
+    ap.add_argument("--emulation-only", action="store_true")
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("--only", nargs="*", help="recompile only these sources (file names under csrc/)")
     args = ap.parse_args(argv)
-    print(build_hip(args.jobs, args.only))
-    print(build_emulation(args.asan))
+    if not args.emulation_only:
+        print(build_hip(args.jobs, args.only))
+    print(build_emulation(args.asan, args.tsan))
     return 0
 
 

@@ -20,6 +20,7 @@
 #include "launch.h"
 #include "pmg.h"
 #include "problem.h"
+#include "tab_layout.h"
 
 using namespace pmg;
 
@@ -354,46 +355,6 @@ int vcycle_any(pmg_problem *pr, int mg_prec, const double *r, double *z, hipStre
 }
 
 template <typename T>
-void bind_tabs(DevTabs<T> &d, const Tables &t, T *base, const std::vector<size_t> &off) {
-  size_t k = 0;
-  for (size_t l = 0; l < t.lev.size(); ++l) {
-    d.Kp[l] = base + off[k++];
-    d.Mp[l] = base + off[k++];
-    d.invD[l] = base + off[k++];
-    d.Tp[l] = base + off[k++];
-    d.TpT[l] = base + off[k++];
-  }
-  d.Kr = base + off[k++];
-  d.Mr = base + off[k++];
-  d.Kt = base + off[k++];
-  d.Mt = base + off[k++];
-  d.W1 = base + off[k++];
-  d.Wr = base + off[k++];
-}
-
-// concatenated tables (each block padded to 32 entries) and their offsets
-void flatten_tabs(const Tables &t, std::vector<double> &flat, std::vector<size_t> &off) {
-  auto put = [&](const dvec &v) {
-    off.push_back(flat.size());
-    flat.insert(flat.end(), v.begin(), v.end());
-    flat.resize((flat.size() + 31) / 32 * 32 + 32, 0.0);
-  };
-  for (const PLevel &L : t.lev) {
-    put(L.Kp);
-    put(L.Mp);
-    put(L.invD);
-    put(L.Tp);
-    put(L.TpT);
-  }
-  put(t.Kr);
-  put(t.Mr);
-  put(t.Kt);
-  put(t.Mt);
-  put(t.W1);
-  put(t.Wr);
-}
-
-template <typename T>
 int dev_alloc(pmg_problem *pr, T **out, size_t count) {
   void *ptr = nullptr;
   PMG_HIP(hipMalloc(&ptr, count * sizeof(T) + 64));
@@ -566,12 +527,19 @@ void pmg_default_config(pmg_config *cfg) {
   cfg->max_iter = 200;
   cfg->rtol = 1e-8;
   cfg->n_omega = 0;
+  cfg->patch_lanes = PMG_LANES_AUTO;
 }
 
-int pmg_setup_mesh(int dim, int n, int n_hlevels, const double *vertices, pmg_mesh **out) {
-  if (!out) return fail(PMG_ERR_INVALID_ARG, "out is NULL");
+int pmg_setup_mesh(int dim, const int32_t *n_cells, int n_hlevels, const double *vertices, pmg_mesh **out) {
+  if (!out || !n_cells) return fail(PMG_ERR_INVALID_ARG, "n_cells or out is NULL");
   if (dim != 2 && dim != 3) return fail(PMG_ERR_INVALID_ARG, "dim must be 2 or 3, got %d", dim);
-  if (n < 2 || n > 1024) return fail(PMG_ERR_INVALID_ARG, "n must be in [2, 1024], got %d", n);
+  for (int d = 0; d < dim; ++d)
+    if (n_cells[d] < 2 || n_cells[d] > 1024)
+      return fail(PMG_ERR_INVALID_ARG, "n_cells[%d] must be in [2, 1024], got %d", d, n_cells[d]);
+  for (int d = 1; d < dim; ++d)
+    if (n_cells[d] != n_cells[0])
+      return fail(PMG_ERR_UNSUPPORTED, "meshes with different cell counts per direction are not supported");
+  const int n = n_cells[0];
   if (n_hlevels < 0) return fail(PMG_ERR_INVALID_ARG, "n_hlevels must be >= 0");
   std::vector<int> sizes{n};
   while (sizes.back() % 2 == 0 && sizes.back() > 3 && (n_hlevels == 0 || (int)sizes.size() < n_hlevels))
@@ -639,6 +607,8 @@ int pmg_setup_dofmap(const pmg_mesh *m, int degree, const int32_t *p_levels, int
   if (c.max_iter < 1) return fail(PMG_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (!(c.rtol > 0.0) || !(c.rtol < 1.0)) return fail(PMG_ERR_INVALID_ARG, "rtol must be in (0, 1)");
   if (c.n_omega < 0 || c.n_omega > (int)deg.size()) return fail(PMG_ERR_INVALID_ARG, "n_omega out of range");
+  if (c.patch_lanes != PMG_LANES_AUTO && c.patch_lanes != PMG_LANES_NARROW && c.patch_lanes != PMG_LANES_WIDE)
+    return fail(PMG_ERR_INVALID_ARG, "patch_lanes unknown");
   for (int i = 1; i < c.n_omega; ++i)
     if (!(c.omega[i] > 0.0 && c.omega[i] < 2.0)) return fail(PMG_ERR_INVALID_ARG, "omega[%d] must be in (0, 2)", i);
   const long mm = (long)degree * m->n + 1;
@@ -765,6 +735,7 @@ int pmg_device_init(pmg_problem *pr) {
   PMG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pr->device));
   pr->arena.lds_max = (size_t)lds;
   pr->arena.ncu = ncu > 0 ? ncu : 256;
+  pr->arena.patch_lanes = pr->cfg.patch_lanes;
   int rc = PMG_OK;
   auto bail = [&](int code) {
     release(pr);

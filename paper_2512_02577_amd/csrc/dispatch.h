@@ -73,5 +73,11 @@ inline int hierarchy_code(int p, const int *deg, int L) {
 constexpr int patch_threads(int p) { return p <= 2 ? 64 : (p <= 4 ? 128 : 256); }
 constexpr int apply_threads(int p) { return p <= 2 ? 128 : 128; }
 
+// Lanes per patch and per cell of the general (metric) path: FP64 patches of degree >= 5
+// fit one per CU in LDS, so they get 8 waves (the short stages split their outputs over
+// them).
+constexpr int metric_patch_threads(int p, int tbytes) { return p <= 2 ? 128 : (tbytes == 8 && p >= 5 ? 512 : 256); }
+constexpr int metric_apply_threads(int p) { return p <= 3 ? 128 : 256; }
+
 
 }  // namespace pmg

@@ -1,27 +1,106 @@
 // CPU emulation of the kernel bodies (validation build, not part of libpmg.so).
 //
-// Runs the same templated bodies the HIP kernels run, one workgroup at a time with a
-// single thread (NT = 1) and an exactly sized heap arena in place of LDS, so that index
-// arithmetic, LDS layouts and tables can be checked against the oracle and under a
-// bounds checker on a machine without a GPU.  Only the test suite loads it.
+// Runs the same templated bodies the HIP kernels run, one workgroup at a time, with an
+// exactly sized heap arena in place of LDS, so that index arithmetic, LDS layouts, tables
+// and the workgroup's barriers can be checked against the oracle and under AddressSanitizer
+// / ThreadSanitizer on a machine without a GPU.  A workgroup runs either on one thread
+// (NT = 1: every lane loop sequential) or on a team of NT host threads, one per lane, with
+// a barrier for every workgroup barrier of the body: this executes the lane-count dependent
+// paths (split stages, strided per-lane reads, read-ahead registers) exactly as the device
+// launches them.  Only the test suite loads it.
+//
+// Lane codes of the entry points: 0 = one lane; 1 = the lane count of the library's
+// launch of that body (patch_threads, apply_threads, ...); 2 = 256 lanes (the latency
+// variant of the patch smoother).  Table modes: 0 = every 1D table in its own exactly sized
+// vector; 1 = the library's concatenated table block (tab_layout.h).
+#include <pthread.h>
+
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "bodies_metric.h"
+#include "constants.h"
 #include "dispatch.h"
 #include "geometry.h"
 #include "host_tables.h"
+#include "tab_layout.h"
 
 using namespace pmg;
 
 namespace {
 
+// NT host threads standing in for the lanes of one workgroup.
+class Team final : public HostTeam {
+ public:
+  explicit Team(int nt) : nt_(nt), slot_(nt, 0.0) { pthread_barrier_init(&bar_, nullptr, (unsigned)nt); }
+  ~Team() override { pthread_barrier_destroy(&bar_); }
+  void sync() override { pthread_barrier_wait(&bar_); }
+  double sum(int tid, double v) override {
+    slot_[tid] = v;
+    sync();
+    double s = 0.0;
+    for (double x : slot_) s += x;
+    sync();
+    return s;
+  }
+  template <class F>
+  void run(const F &f) {
+    std::vector<std::thread> th;
+    th.reserve(nt_);
+    for (int t = 0; t < nt_; ++t)
+      th.emplace_back([this, &f, t] {
+        host_team = this;
+        f(t);
+        host_team = nullptr;
+      });
+    for (auto &x : th) x.join();
+  }
+
+ private:
+  int nt_;
+  std::vector<double> slot_;
+  pthread_barrier_t bar_;
+};
+
+// Runs f(tid) for the NT lanes of a workgroup.
+template <int NT, class F>
+void run_lanes(const F &f) {
+  if constexpr (NT == 1) {
+    f(0);
+  } else {
+    Team t(NT);
+    t.run(f);
+  }
+}
+
+// A launch of nblk workgroups on one arena (the workgroups run one after the other, with a
+// barrier between them, as the global-arena kernels loop).
+template <int NT, class F>
+void launch(int nblk, std::vector<double> &arena, const F &body) {
+  run_lanes<NT>([&](int tid) {
+    for (int blk = 0; blk < nblk; ++blk) {
+      body(tid, blk, arena.data());
+      PMG_SYNC();
+    }
+  });
+}
+
 struct HostTabs {
   Tables t;
   DevTabs<double> d{};
-  void bind() {
+  std::vector<double> flat;  // table mode 1: the library's block
+  void bind(int mode) {
     std::memset(&d, 0, sizeof(d));
+    if (mode == 1) {
+      std::vector<size_t> off;
+      flat.clear();
+      flatten_tabs(t, flat, off);
+      bind_tabs(d, t, flat.data(), off);
+      return;
+    }
     for (size_t l = 0; l < t.lev.size(); ++l) {
       d.Kp[l] = t.lev[l].Kp.data();
       d.Mp[l] = t.lev[l].Mp.data();
@@ -38,47 +117,68 @@ struct HostTabs {
   }
 };
 
-bool make_tabs(HostTabs &h, int dim, int p, const int *deg, int L, const double *omega, int n_coarse) {
+void make_tabs(HostTabs &h, int dim, int p, const int *deg, int L, const double *omega, int n_coarse, int mode) {
   std::vector<int> degrees(deg, deg + L);
   dvec om;
   if (omega) om.assign(omega, omega + L);
   build_tables(dim, p, degrees, om, n_coarse, h.t);
-  h.bind();
-  return true;
+  h.bind(mode);
 }
 
 double cscale(int dim, int n) { return dim == 3 ? 1.0 / n : 1.0; }
+
+// first vertex coordinate and patch count per axis of color col (the library's do_smooth)
+template <typename A>
+void color_range(int dim, int n, int col, A &a, int first_odd, int first_even) {
+  a.n_patch = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (d >= dim) {
+      a.first[d] = 0;
+      a.cnt[d] = 1;
+      continue;
+    }
+    a.first[d] = (col >> d) & 1 ? first_odd : first_even;
+    a.cnt[d] = a.first[d] <= n - 1 ? (n - 1 - a.first[d]) / 2 + 1 : 0;
+    a.n_patch *= a.cnt[d];
+  }
+}
 
 template <int DIM>
 struct EmuSmooth {
   template <int P, class H>
   struct F {
-    static int run(const SmoothArgs<double> &base, int n, int color_dir, bool local_only, int n_blocks) {
-      using B = PatchBody<DIM, double, 1, P, H>;
+    template <int NT, bool ONE>
+    static int go(const SmoothArgs<double> &base, int n, int color_dir, bool local_only, int n_blocks) {
+      using B = PatchBody<DIM, double, NT, P, H>;
       std::vector<double> lds(B::arena(base.n_iter));  // exactly what the device launch gets
       if (local_only) {
-        for (int blk = 0; blk < n_blocks; ++blk) B::local_only(0, blk, lds.data(), base);
+        launch<NT>(n_blocks, lds, [&](int tid, int blk, double *ar) { B::local_only(tid, blk, ar, base); });
         return 0;
       }
       const int ncol = 1 << DIM;
       for (int ci = 0; ci < ncol; ++ci) {
         const int col = color_dir > 0 ? ci : ncol - 1 - ci;
         SmoothArgs<double> a = base;
-        a.n_patch = 1;
-        for (int d = 0; d < 3; ++d) {
-          if (d >= DIM) {
-            a.first[d] = 0;
-            a.cnt[d] = 1;
-            continue;
-          }
-          const int bit = (col >> d) & 1;
-          a.first[d] = bit ? 1 : 2;
-          a.cnt[d] = a.first[d] <= n - 1 ? (n - 1 - a.first[d]) / 2 + 1 : 0;
-          a.n_patch *= a.cnt[d];
-        }
-        for (int blk = 0; blk < a.n_patch; ++blk) B::smooth_patch(0, blk, lds.data(), a);
+        color_range(DIM, n, col, a, 1, 2);
+        if (a.n_patch == 0) continue;
+        launch<NT>(a.n_patch, lds,
+                   [&](int tid, int blk, double *ar) { B::template smooth_patch<ONE>(tid, blk, ar, a); });
       }
       return 0;
+    }
+    static int run(const SmoothArgs<double> &base, int n, int color_dir, bool local_only, int n_blocks, int lanes,
+                   int one) {
+      const bool o = one != 0;
+      if (o && (base.full || base.n_iter != 1)) return -3;  // ONE compiles the default solver only
+      switch (lanes) {
+        case 0: return o ? go<1, true>(base, n, color_dir, local_only, n_blocks)
+                         : go<1, false>(base, n, color_dir, local_only, n_blocks);
+        case 1: return o ? go<patch_threads(P), true>(base, n, color_dir, local_only, n_blocks)
+                         : go<patch_threads(P), false>(base, n, color_dir, local_only, n_blocks);
+        case 2: return o ? go<256, true>(base, n, color_dir, local_only, n_blocks)
+                         : go<256, false>(base, n, color_dir, local_only, n_blocks);
+        default: return -1;
+      }
     }
   };
 };
@@ -87,14 +187,20 @@ template <int DIM, bool RESID>
 struct EmuApply {
   template <int P>
   struct F {
-    static int run(ApplyArgs<double> a) {
+    template <int NT>
+    static int go(ApplyArgs<double> a) {
       constexpr int TC = tile_cells(P);
-      using B = ApplyBody<DIM, double, 1, P, TC, RESID>;
+      using B = ApplyBody<DIM, double, NT, P, TC, RESID>;
       std::vector<double> lds(B::size);
       a.ntile = (a.n + TC - 1) / TC;
       a.n_tiles = DIM == 3 ? a.ntile * a.ntile * a.ntile : a.ntile * a.ntile;
-      for (int blk = 0; blk < a.n_tiles; ++blk) B::run(0, blk, lds.data(), a);
+      launch<NT>(a.n_tiles, lds, [&](int tid, int blk, double *ar) { B::run(tid, blk, ar, a); });
       return 0;
+    }
+    static int run(const ApplyArgs<double> &a, int lanes) {
+      if (lanes == 0) return go<1>(a);
+      if (lanes == 1) return go<apply_threads(P)>(a);
+      return -1;
     }
   };
 };
@@ -136,8 +242,9 @@ template <int DIM>
 struct EmuMetricApply {
   template <int P>
   struct F {
-    static int run(MetricApplyArgs<double, double> base) {
-      using B = MetricApplyBody<DIM, double, double, 1, P>;
+    template <int NT>
+    static int go(const MetricApplyArgs<double, double> &base) {
+      using B = MetricApplyBody<DIM, double, double, NT, P>;
       std::vector<double> lds(B::size);
       const int ncol = 1 << DIM, n = base.n;
       for (int col = 0; col < ncol; ++col) {
@@ -149,9 +256,15 @@ struct EmuMetricApply {
           a.cnt[d] = a.first[d] <= n - 1 ? (n - 1 - a.first[d]) / 2 + 1 : 0;
           a.n_cells *= a.cnt[d];
         }
-        for (int blk = 0; blk < a.n_cells; ++blk) B::run(0, blk, lds.data(), a);
+        if (a.n_cells == 0) continue;
+        launch<NT>(a.n_cells, lds, [&](int tid, int blk, double *ar) { B::run(tid, blk, ar, a); });
       }
       return 0;
+    }
+    static int run(const MetricApplyArgs<double, double> &base, int lanes) {
+      if (lanes == 0) return go<1>(base);
+      if (lanes == 1) return go<metric_apply_threads(P)>(base);
+      return -1;
     }
   };
 };
@@ -160,27 +273,35 @@ template <int DIM>
 struct EmuMetricSmooth {
   template <int P, class H>
   struct F {
-    static int run(const MetricSmoothArgs<double, double> &base, int n, int color_dir, bool local_only, int nb) {
-      using B = MetricPatchBody<DIM, double, double, 1, P, H>;
+    template <int NT, bool ONE>
+    static int go(const MetricSmoothArgs<double, double> &base, int n, int color_dir, bool local_only, int nb) {
+      using B = MetricPatchBody<DIM, double, double, NT, P, H>;
       std::vector<double> lds(B::arena(base.n_iter));  // exactly what the device launch gets
       if (local_only) {
-        for (int blk = 0; blk < nb; ++blk) B::local_only(0, blk, lds.data(), base);
+        launch<NT>(nb, lds, [&](int tid, int blk, double *ar) { B::local_only(tid, blk, ar, base); });
         return 0;
       }
       const int ncol = 1 << DIM;
       for (int ci = 0; ci < ncol; ++ci) {
         const int col = color_dir > 0 ? ci : ncol - 1 - ci;
         MetricSmoothArgs<double, double> a = base;
-        a.n_patch = 1;
-        for (int d = 0; d < 3; ++d) {
-          if (d >= DIM) { a.first[d] = 0; a.cnt[d] = 1; continue; }
-          a.first[d] = (col >> d) & 1 ? 1 : 2;
-          a.cnt[d] = a.first[d] <= n - 1 ? (n - 1 - a.first[d]) / 2 + 1 : 0;
-          a.n_patch *= a.cnt[d];
-        }
-        for (int blk = 0; blk < a.n_patch; ++blk) B::smooth_patch(0, blk, lds.data(), a);
+        color_range(DIM, n, col, a, 1, 2);
+        if (a.n_patch == 0) continue;
+        launch<NT>(a.n_patch, lds,
+                   [&](int tid, int blk, double *ar) { B::template smooth_patch<ONE>(tid, blk, ar, a); });
       }
       return 0;
+    }
+    static int run(const MetricSmoothArgs<double, double> &base, int n, int color_dir, bool local_only, int nb,
+                   int lanes, int one) {
+      const bool o = one != 0;
+      if (o && (base.full || base.n_iter != 1)) return -3;
+      constexpr int W = metric_patch_threads(P, sizeof(double));
+      if (lanes == 0) return o ? go<1, true>(base, n, color_dir, local_only, nb)
+                               : go<1, false>(base, n, color_dir, local_only, nb);
+      if (lanes == 1) return o ? go<W, true>(base, n, color_dir, local_only, nb)
+                               : go<W, false>(base, n, color_dir, local_only, nb);
+      return -1;
     }
   };
 };
@@ -213,7 +334,7 @@ extern "C" {
 // Metric-path apply (resid: out = b - A u) on one level; verts: (n+1)^d x d or NULL for
 // the Cartesian box; coef: per Gauss point of degree p, or NULL.
 int pmgemu_metric_apply(int dim, int n, int p, const double *verts, const double *coef, int resid, const double *u,
-                        const double *b, double *out) {
+                        const double *b, double *out, int lanes) {
   dvec V = verts ? dvec(verts, verts + (size_t)(dim == 3 ? (n + 1) * (n + 1) * (n + 1) : (n + 1) * (n + 1)) * dim)
                  : cartesian_vertices(dim, n);
   dvec G;
@@ -230,15 +351,15 @@ int pmgemu_metric_apply(int dim, int n, int p, const double *verts, const double
   a.sign = resid ? -1.0 : 1.0;
   a.u = u;
   a.out = out;
-  if (dim == 3) return dispatch_degree<EmuMetricApply<3>::F>(p, a);
-  return dispatch_degree<EmuMetricApply<2>::F>(p, a);
+  if (dim == 3) return dispatch_degree<EmuMetricApply<3>::F>(p, a, lanes);
+  return dispatch_degree<EmuMetricApply<2>::F>(p, a, lanes);
 }
 
 // Metric-path smoother (all colors) or local solve (nb > 0: r/d blocks) on one level.
 // coefs: L pointers (Gauss-point coefficient per p-level, NULL entries for mu = 1).
 int pmgemu_metric_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
                          int color_dir, const double *verts, const double *const *coefs, double *u, const double *b,
-                         int nb, const double *r, double *d) {
+                         int nb, const double *r, double *d, int lanes, int one) {
   dvec V = verts ? dvec(verts, verts + (size_t)(dim == 3 ? (n + 1) * (n + 1) * (n + 1) : (n + 1) * (n + 1)) * dim)
                  : cartesian_vertices(dim, n);
   Tables tab;
@@ -270,17 +391,15 @@ int pmgemu_metric_smooth(int dim, int n, int p, const int *deg, int L, const dou
   a.d_blocks = d;
   const int code = hierarchy_code(p, deg, L);
   if (code < 0) return -2;
-  if (dim == 3) return dispatch_hierarchy<EmuMetricSmooth<3>::F>(p, code, a, n, color_dir, nb > 0, nb);
-  return dispatch_hierarchy<EmuMetricSmooth<2>::F>(p, code, a, n, color_dir, nb > 0, nb);
+  if (dim == 3) return dispatch_hierarchy<EmuMetricSmooth<3>::F>(p, code, a, n, color_dir, nb > 0, nb, lanes, one);
+  return dispatch_hierarchy<EmuMetricSmooth<2>::F>(p, code, a, n, color_dir, nb > 0, nb, lanes, one);
 }
-
-
 
 // One smoother application (all colors) on a single Cartesian level of n^dim cells.
 int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
-                  int color_dir, double *u, const double *b) {
+                  int color_dir, double *u, const double *b, int lanes, int one, int tabmode) {
   HostTabs h;
-  make_tabs(h, dim, p, deg, L, omega, n);
+  make_tabs(h, dim, p, deg, L, omega, n, tabmode);
   SmoothArgs<double> a{};
   a.tb = h.d;
   a.c = cscale(dim, n);
@@ -292,14 +411,14 @@ int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *om
   a.b = b;
   const int code = hierarchy_code(p, deg, L);
   if (code < 0) return -2;
-  if (dim == 3) return dispatch_hierarchy<EmuSmooth<3>::F>(p, code, a, n, color_dir, false, 0);
-  return dispatch_hierarchy<EmuSmooth<2>::F>(p, code, a, n, color_dir, false, 0);
+  if (dim == 3) return dispatch_hierarchy<EmuSmooth<3>::F>(p, code, a, n, color_dir, false, 0, lanes, one);
+  return dispatch_hierarchy<EmuSmooth<2>::F>(p, code, a, n, color_dir, false, 0, lanes, one);
 }
 
 int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
-                       int n_blocks, const double *r, double *d) {
+                       int n_blocks, const double *r, double *d, int lanes, int tabmode) {
   HostTabs h;
-  make_tabs(h, dim, p, deg, L, omega, n);
+  make_tabs(h, dim, p, deg, L, omega, n, tabmode);
   SmoothArgs<double> a{};
   a.tb = h.d;
   a.c = cscale(dim, n);
@@ -311,11 +430,11 @@ int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const doubl
   a.d_blocks = d;
   const int code = hierarchy_code(p, deg, L);
   if (code < 0) return -2;
-  if (dim == 3) return dispatch_hierarchy<EmuSmooth<3>::F>(p, code, a, n, 1, true, n_blocks);
-  return dispatch_hierarchy<EmuSmooth<2>::F>(p, code, a, n, 1, true, n_blocks);
+  if (dim == 3) return dispatch_hierarchy<EmuSmooth<3>::F>(p, code, a, n, 1, true, n_blocks, lanes, 0);
+  return dispatch_hierarchy<EmuSmooth<2>::F>(p, code, a, n, 1, true, n_blocks, lanes, 0);
 }
 
-int pmgemu_apply(int dim, int n, int p, int resid, const double *u, const double *b, double *out) {
+int pmgemu_apply(int dim, int n, int p, int resid, const double *u, const double *b, double *out, int lanes) {
   Tables t;
   build_tables(dim, p, std::vector<int>{p}, {}, n, t);
   ApplyArgs<double> a{};
@@ -327,8 +446,8 @@ int pmgemu_apply(int dim, int n, int p, int resid, const double *u, const double
   a.b = b;
   a.out = out;
   if (dim == 3)
-    return resid ? dispatch_degree<EmuApply<3, true>::F>(p, a) : dispatch_degree<EmuApply<3, false>::F>(p, a);
-  return resid ? dispatch_degree<EmuApply<2, true>::F>(p, a) : dispatch_degree<EmuApply<2, false>::F>(p, a);
+    return resid ? dispatch_degree<EmuApply<3, true>::F>(p, a, lanes) : dispatch_degree<EmuApply<3, false>::F>(p, a, lanes);
+  return resid ? dispatch_degree<EmuApply<2, true>::F>(p, a, lanes) : dispatch_degree<EmuApply<2, false>::F>(p, a, lanes);
 }
 
 int pmgemu_transfer(int dim, int nc, int p, int restrict_, const double *in, double *out) {
@@ -349,11 +468,14 @@ int pmgemu_transfer(int dim, int nc, int p, int restrict_, const double *in, dou
   return restrict_ ? dispatch_degree<EmuTransfer<2, true>::F>(p, a) : dispatch_degree<EmuTransfer<2, false>::F>(p, a);
 }
 
-int pmgemu_coarse_solve(int dim, int n0, int p, const double *r, double *z) {
+// Coarse solve by fast diagonalization; lanes 0: one lane on the global work vectors,
+// 1: the library's workgroup (kCoarseThreads lanes) with the work vectors in its arena.
+int pmgemu_coarse_solve(int dim, int n0, int p, const double *r, double *z, int lanes) {
   Tables t;
   build_tables(dim, p, std::vector<int>{p}, {}, n0, t);
   const int m = t.m0;
-  std::vector<double> w1((size_t)(dim == 3 ? m * m * m : m * m)), w2(w1.size());
+  const size_t tot = dim == 3 ? (size_t)m * m * m : (size_t)m * m;
+  std::vector<double> w1(tot), w2(tot), lds(2 * tot);
   CoarseArgs<double> a{};
   a.S = t.S0.data();
   a.lam = t.lam0.data();
@@ -364,10 +486,21 @@ int pmgemu_coarse_solve(int dim, int n0, int p, const double *r, double *z) {
   a.z = z;
   a.w1 = w1.data();
   a.w2 = w2.data();
-  if (dim == 3)
-    CoarseBody<3, double, 1>::run(0, a);
-  else
-    CoarseBody<2, double, 1>::run(0, a);
+  if (lanes == 0) {
+    if (dim == 3)
+      CoarseBody<3, double, 1>::run(0, a);
+    else
+      CoarseBody<2, double, 1>::run(0, a);
+    return 0;
+  }
+  if (lanes != 1) return -1;
+  constexpr int NT = kCoarseThreads;
+  run_lanes<NT>([&](int tid) {
+    if (dim == 3)
+      CoarseBody<3, double, NT>::run(tid, a, lds.data(), (int)lds.size());
+    else
+      CoarseBody<2, double, NT>::run(tid, a, lds.data(), (int)lds.size());
+  });
   return 0;
 }
 

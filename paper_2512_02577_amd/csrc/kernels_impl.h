@@ -128,8 +128,10 @@ struct SmoothL {
         using B = PatchBody<DIM, T, patch_threads(P), P, H>;
         const size_t bytes = B::arena(a.n_iter) * sizeof(T);
         const bool one = a.full == 0 && a.n_iter == 1;
+        // patch_lanes: 0 by launch size, 1 always the per-degree count, 2 always 256
+        const bool wide = ar.patch_lanes == 2 || (ar.patch_lanes == 0 && a.n_patch <= kWideLaunch * ar.ncu);
         if constexpr (patch_threads(P) < 256)
-          if (a.n_patch <= kWideLaunch * ar.ncu && bytes <= ar.lds_max)
+          if (wide && bytes <= ar.lds_max)
             return one ? launch_arena(k_smooth_w<DIM, T, P, H, true>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256,
                                       bytes, ar, s, a)
                        : launch_arena(k_smooth_w<DIM, T, P, H, false>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256,

@@ -14,11 +14,6 @@ namespace pmg {
 
 namespace mdetail {
 
-// Lanes per patch: FP64 patches of degree >= 5 fit one per CU in LDS, so they get 8 waves
-// (the short stages split their outputs over them).
-constexpr int metric_patch_threads(int p, int tbytes) { return p <= 2 ? 128 : (tbytes == 8 && p >= 5 ? 512 : 256); }
-constexpr int metric_apply_threads(int p) { return p <= 3 ? 128 : 256; }
-
 template <typename T>
 __device__ inline T *lds_arena() {
   extern __shared__ __align__(16) unsigned char smem[];

@@ -5,6 +5,7 @@
 
 #include "bodies.h"
 #include "bodies_metric.h"
+#include "constants.h"
 
 namespace pmg {
 
@@ -15,13 +16,12 @@ struct Arena {
   int slots = 0;           // workgroups the global buffer has room for
   size_t lds_max = 0;      // bytes of LDS a workgroup may use on this device
   int ncu = 256;           // compute units of the device
+  int patch_lanes = 0;     // PMG_LANES_*: lanes per patch of the Cartesian smoother
 };
 
-// Patch launches with at most this many patches per CU use the 256-lane latency variant.
+// Patch launches with at most this many patches per CU use the 256-lane latency variant
+// (unless the problem's configuration fixes the lane count).
 constexpr int kWideLaunch = 4;
-
-// Threads of the coarse-solve workgroup.
-constexpr int kCoarseThreads = 512;
 
 // Bytes of LDS a workgroup may use on the current device (queried once per process).
 inline size_t device_lds_limit() {

@@ -8,8 +8,10 @@
 // with wave-uniform addresses (read through the scalar cache) and a compile-time
 // sparsity pattern: row o touches columns [Pat::lo(o), Pat::hi(o)) only.
 //
-// The bodies are __host__ __device__: on the device tid/NT are the workgroup's threads,
-// on the host (NT = 1) the same code runs sequentially for index and bounds checks.
+// The bodies are __host__ __device__: on the device tid/NT are the workgroup's threads;
+// on the host the same code runs for index, bounds and race checks, either sequentially
+// (NT = 1) or with one host thread per lane (a HostTeam, whose barrier stands in for the
+// workgroup barrier).
 #pragma once
 
 #if defined(__HIPCC__)
@@ -27,7 +29,21 @@
 // then become scalar loads into SGPRs instead of per-lane vector loads.
 #define PMG_CONST_AS __attribute__((address_space(4)))
 #else
-#define PMG_SYNC() ((void)0)
+namespace pmg {
+// Host runs with one thread per lane register the team of the calling thread here; the
+// workgroup barrier and the workgroup sum then go through it.  Without a team (NT = 1)
+// the barrier is a no-op.
+struct HostTeam {
+  virtual ~HostTeam() = default;
+  virtual void sync() = 0;
+  virtual double sum(int tid, double v) = 0;  // every lane gets the sum in lane order
+};
+inline thread_local HostTeam *host_team = nullptr;
+inline void host_sync() {
+  if (host_team) host_team->sync();
+}
+}  // namespace pmg
+#define PMG_SYNC() ::pmg::host_sync()
 #define PMG_CONST_AS
 #endif
 
@@ -639,7 +655,8 @@ PMG_INLINE void dcontract_sub(int tid, const T *in, T *out, const T *base, const
 }
 
 // Sum over the workgroup of one value per lane; every lane gets the total.  red: NT/64
-// (at least 1) elements of LDS scratch.  On the host (NT = 1) the value itself.
+// (at least 1) elements of LDS scratch.  On the host the value itself (NT = 1) or the
+// team's sum.
 template <int NT, typename T>
 PMG_INLINE T block_sum(int tid, T v, T *red) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -654,9 +671,13 @@ PMG_INLINE T block_sum(int tid, T v, T *red) {
   __syncthreads();
   return s;
 #else
-  (void)tid;
   (void)red;
-  return v;
+  if constexpr (NT == 1) {
+    (void)tid;
+    return v;
+  } else {
+    return (T)host_team->sum(tid, (double)v);
+  }
 #endif
 }
 

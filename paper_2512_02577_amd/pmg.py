@@ -21,6 +21,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CON
     0, -1, -2, -3, -4, -5, -6, -7)
 FP64, FP32, FP32_BF16 = 0, 1, 2
 LOCAL_HALF_V, LOCAL_FULL_V = 0, 1
+LANES_AUTO, LANES_NARROW, LANES_WIDE = 0, 1, 2
 
 
 class PmgError(RuntimeError):
@@ -32,7 +33,7 @@ class PmgError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("local_solver", ctypes.c_int), ("n_local_iter", ctypes.c_int), ("n_pre", ctypes.c_int),
                 ("n_post", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("n_omega", ctypes.c_int), ("omega", ctypes.c_double * 8)]
+                ("n_omega", ctypes.c_int), ("omega", ctypes.c_double * 8), ("patch_lanes", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -55,7 +56,7 @@ def lib() -> ctypes.CDLL:
         sig = {
             "pmg_last_error": (ctypes.c_char_p, []),
             "pmg_default_config": (None, [P(Config)]),
-            "pmg_setup_mesh": (_ip, [_ip, _ip, _ip, P(_dp), P(_vp)]),
+            "pmg_setup_mesh": (_ip, [_ip, P(ctypes.c_int32), _ip, P(_dp), P(_vp)]),
             "pmg_mesh_levels": (_ip, [_vp, P(_ip), P(_ip), P(ctypes.c_int32)]),
             "pmg_destroy_mesh": (None, [_vp]),
             "pmg_setup_dofmap": (_ip, [_vp, _ip, P(ctypes.c_int32), _ip, P(Config), P(_vp)]),
@@ -183,13 +184,15 @@ class Problem:
             self.handle = None
 
 
-def setup_mesh(dim: int, n: int, n_hlevels: int = 0, vertices: np.ndarray | None = None) -> Mesh:
+def setup_mesh(dim: int, n, n_hlevels: int = 0, vertices: np.ndarray | None = None) -> Mesh:
+    """n: cells per direction (an int, or a sequence of dim counts)."""
     h = ctypes.c_void_p()
     vp = None
     if vertices is not None:
         vertices = np.ascontiguousarray(vertices, dtype=np.float64)
         vp = vertices.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    _check(lib().pmg_setup_mesh(dim, n, n_hlevels, vp, ctypes.byref(h)))
+    cells = [int(n)] * 3 if np.isscalar(n) else [int(x) for x in n] + [0] * (3 - len(n))
+    _check(lib().pmg_setup_mesh(dim, (ctypes.c_int32 * 3)(*cells), n_hlevels, vp, ctypes.byref(h)))
     return Mesh(h)
 
 

@@ -129,3 +129,23 @@ def test_batch_rejects_problems_without_device_state():
     assert L.pmg_batch_vcycle(None, pmg.FP32, None, None, None) == pmg.ERR_INVALID_ARG
     assert L.pmg_batch_stats(None, pmg.FP32, None, None) == pmg.ERR_INVALID_ARG
     L.pmg_destroy_batch(None)
+
+
+def test_cell_counts_per_direction_and_lane_option():
+    assert pmg.setup_mesh(3, (8, 8, 8)).levels() == [2, 4, 8]
+    assert pmg.setup_mesh(2, (6, 6)).levels() == [3, 6]
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.setup_mesh(3, (8, 8, 4))  # the kernels index cubic node grids only
+    assert e.value.status == pmg.ERR_UNSUPPORTED
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.setup_mesh(3, (8, 1, 8))
+    assert e.value.status == pmg.ERR_INVALID_ARG
+    assert pmg.lib().pmg_setup_mesh(3, None, 0, None, ctypes.byref(ctypes.c_void_p())) == pmg.ERR_INVALID_ARG
+    for lanes in (pmg.LANES_AUTO, pmg.LANES_NARROW, pmg.LANES_WIDE):
+        cfg = pmg.default_config()
+        cfg.patch_lanes = lanes
+        pmg.setup_dofmap(pmg.setup_mesh(3, 4), 4, None, cfg)
+    cfg.patch_lanes = 3
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.setup_dofmap(pmg.setup_mesh(3, 4), 4, None, cfg)
+    assert e.value.status == pmg.ERR_INVALID_ARG

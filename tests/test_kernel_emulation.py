@@ -1,7 +1,13 @@
-"""The HIP kernels' bodies executed on the CPU (one thread per workgroup, exactly sized
-arena) against the oracle.  This pins the index arithmetic, LDS layouts and 1D tables
+"""The HIP kernels' bodies executed on the CPU against the oracle, with an exactly sized
+arena, either on one thread per workgroup or on one host thread per lane at the lane
+counts of the library's launches (a barrier for every workgroup barrier, the workgroup
+sum over the lanes).  This pins the index arithmetic, LDS layouts, 1D tables and the
+lane-count dependent paths (split stages, strided per-lane reads and read-ahead registers)
 of every kernel family before any GPU run; the GPU parity tests then check the same
-bodies on gfx950."""
+bodies on gfx950.
+
+Lane codes: 0 one lane, 1 the library's lane count of that body, 2 the 256-lane latency
+variant of the patch smoother."""
 import ctypes
 import os
 
@@ -39,16 +45,17 @@ def cd(a):
     return (ctypes.c_double * len(a))(*a)
 
 
+@pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("dim,n,p", [(2, 4, 1), (2, 5, 2), (2, 5, 3), (2, 3, 7), (2, 3, 8), (3, 3, 1), (3, 5, 2),
                                      (3, 4, 3), (3, 3, 4), (3, 3, 5), (3, 2, 6), (3, 2, 7), (3, 2, 8)])
-def test_apply_and_residual(emu, dim, n, p):
+def test_apply_and_residual(emu, dim, n, p, lanes):
     A = stiffness_matrix(StructuredMesh(dim, n), p)
     u = np.random.default_rng(1).uniform(-1, 1, A.shape[0])
     b = rhs_vector(dim, n, p, 2)
     v = np.zeros_like(u)
     r = np.zeros_like(u)
-    assert emu.pmgemu_apply(dim, n, p, 0, P(u), P(b), P(v)) == 0
-    assert emu.pmgemu_apply(dim, n, p, 1, P(u), P(b), P(r)) == 0
+    assert emu.pmgemu_apply(dim, n, p, 0, P(u), P(b), P(v), lanes) == 0
+    assert emu.pmgemu_apply(dim, n, p, 1, P(u), P(b), P(r), lanes) == 0
     ref = A @ u
     s = abs(ref).max()
     assert abs(v - ref).max() <= 1e-13 * s
@@ -73,8 +80,57 @@ def test_smoother(emu, dim, n, p, lv, local):
             ref = ls.smooth(u0, b, descending=direction < 0)
             u = u0.copy()
             assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), it, direction,
-                                     P(u), P(b)) == 0
+                                     P(u), P(b), 0, 0, 0) == 0
             assert abs(u - ref).max() <= 1e-12 * abs(ref).max()
+
+
+# (dim, n, p, levels): the library's lane counts for every degree; n chosen so that each
+# color has several patches
+LANE_CASES = [(2, 4, 2, None), (2, 3, 3, [1, 2, 3]), (2, 3, 7, None), (3, 3, 1, None), (3, 4, 2, None),
+              (3, 3, 3, None), (3, 3, 4, None), (3, 3, 4, [1, 2, 3, 4]), (3, 2, 5, None), (3, 2, 6, None),
+              (3, 2, 7, None), (3, 2, 8, None)]
+
+
+@pytest.mark.parametrize("dim,n,p,lv", LANE_CASES)
+def test_smoother_lane_teams(emu, dim, n, p, lv):
+    # the default local solver in its own compiled variant (one = 1) and the general variant,
+    # at the library's narrow lane count and at 256 lanes, on both table layouts
+    deg = lv or p_hierarchy(p)
+    om = [1.0] + [0.5 + 0.05 * l for l in range(1, len(deg))]
+    ls = LevelSmoother(StructuredMesh(dim, n), deg, omega=om, local="half")
+    b = rhs_vector(dim, n, p, 3)
+    u0 = np.random.default_rng(4).uniform(-1, 1, len(b))
+    for direction in (1, -1):
+        ref = ls.smooth(u0, b, descending=direction < 0)
+        for lanes, one, tabmode in ((1, 1, 1), (2, 1, 0), (1, 0, 0), (2, 0, 1)):
+            u = u0.copy()
+            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), 0, 1, direction, P(u), P(b), lanes, one,
+                                     tabmode) == 0
+            assert abs(u - ref).max() <= 1e-12 * abs(ref).max(), (lanes, one, tabmode, direction)
+
+
+@pytest.mark.parametrize("dim,n,p", [(3, 3, 4), (2, 4, 3), (3, 2, 5)])
+def test_smoother_lane_teams_full_and_richardson(emu, dim, n, p):
+    deg = p_hierarchy(p)
+    om = [1.0] + [0.5 + 0.05 * l for l in range(1, len(deg))]
+    b = rhs_vector(dim, n, p, 5)
+    u0 = np.random.default_rng(6).uniform(-1, 1, len(b))
+    for local, it in (("full", 1), ("half", 2), ("full", 2)):
+        ls = LevelSmoother(StructuredMesh(dim, n), deg, omega=om, local=local, n_local_iter=it)
+        ref = ls.smooth(u0, b)
+        for lanes in (1, 2):
+            u = u0.copy()
+            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), it, 1, P(u), P(b),
+                                     lanes, 0, 1) == 0
+            assert abs(u - ref).max() <= 1e-12 * abs(ref).max(), (local, it, lanes)
+
+
+def test_one_variant_rejects_other_solvers(emu):
+    deg = p_hierarchy(4)
+    om = [1.0, 0.6, 0.6]
+    b = rhs_vector(3, 2, 4, 1)
+    u = np.zeros_like(b)
+    assert emu.pmgemu_smooth(3, 2, 4, ci(deg), 3, cd(om), 1, 1, 1, P(u), P(b), 1, 1, 0) == -3
 
 
 @pytest.mark.parametrize("dim,p", [(2, 3), (3, 4), (3, 2)])
@@ -86,10 +142,12 @@ def test_local_solve(emu, dim, p):
     nd = ls.interior[-1].shape[1]
     r = np.random.default_rng(0).uniform(-1, 1, nb * nd)
     d = np.zeros_like(r)
-    assert emu.pmgemu_local_solve(dim, 3, p, ci(deg), len(deg), cd(om), 0, 1, nb, P(r), P(d)) == 0
-    for j in range(nb):
-        ref = ls.local_solve(j, r[j * nd:(j + 1) * nd])
-        assert abs(d[j * nd:(j + 1) * nd] - ref).max() <= 1e-13 * abs(ref).max()
+    for lanes in (0, 1):
+        d[:] = 0
+        assert emu.pmgemu_local_solve(dim, 3, p, ci(deg), len(deg), cd(om), 0, 1, nb, P(r), P(d), lanes, lanes) == 0
+        for j in range(nb):
+            ref = ls.local_solve(j, r[j * nd:(j + 1) * nd])
+            assert abs(d[j * nd:(j + 1) * nd] - ref).max() <= 1e-13 * abs(ref).max()
 
 
 @pytest.mark.parametrize("dim,nc,p", [(2, 2, 1), (2, 3, 3), (3, 2, 2), (3, 2, 4), (2, 2, 8), (3, 3, 1), (3, 2, 7)])
@@ -110,10 +168,11 @@ def test_h_transfers(emu, dim, nc, p):
 def test_coarse_solve(emu, dim, n0, p):
     pb = MultigridProblem(dim, n0, p)
     r = np.random.default_rng(7).uniform(-1, 1, pb.N)
-    z = np.zeros_like(r)
-    assert emu.pmgemu_coarse_solve(dim, n0, p, P(r), P(z)) == 0
     ref = pb.coarse_solve(r)
-    assert abs(z - ref).max() <= 1e-12 * abs(ref).max()
+    for lanes in (0, 1):
+        z = np.zeros_like(r)
+        assert emu.pmgemu_coarse_solve(dim, n0, p, P(r), P(z), lanes) == 0
+        assert abs(z - ref).max() <= 1e-12 * abs(ref).max()
 
 
 # ---- general path: distorted cells and a variable coefficient -------------------------
@@ -145,10 +204,10 @@ def test_general_apply(emu, dim, n, p, jit, use_coef):
     u = np.random.default_rng(1).uniform(-1, 1, A.shape[0])
     b = rhs_vector(dim, n, p, 2)
     c = _coef(mesh, field, p)
-    for resid in (0, 1):
+    for resid, lanes in ((0, 0), (1, 0), (0, 1), (1, 1)):
         out = np.zeros_like(u)
         assert emu.pmgemu_metric_apply(dim, n, p, P(V) if V is not None else None, P(c) if c is not None else None,
-                                       resid, P(u), P(b), P(out)) == 0
+                                       resid, P(u), P(b), P(out), lanes) == 0
         ref = b - A @ u if resid else A @ u
         assert abs(out - ref).max() <= 1e-13 * abs(ref).max()
 
@@ -162,19 +221,21 @@ def test_general_smoother_and_local_solve(emu, dim, n, p, jit, use_coef):
     carr = (DP * len(deg))(*[P(x) if x is not None else None for x in coefs])
     b = rhs_vector(dim, n, p, 3)
     u0 = np.random.default_rng(4).uniform(-1, 1, len(b))
-    for local, it, direction in (("half", 1, 1), ("full", 2, -1)):
+    for local, it, direction, lanes, one in (("half", 1, 1, 0, 0), ("full", 2, -1, 0, 0), ("half", 1, -1, 1, 1),
+                                             ("full", 2, 1, 1, 0)):
         ls = LevelSmoother(mesh, deg, omega=om, coef=field, local=local, n_local_iter=it)
         u = u0.copy()
         assert emu.pmgemu_metric_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), it, direction,
-                                        P(V) if V is not None else None, carr, P(u), P(b), 0, None, None) == 0
+                                        P(V) if V is not None else None, carr, P(u), P(b), 0, None, None, lanes,
+                                        one) == 0
         ref = ls.smooth(u0, b, descending=direction < 0)
-        assert abs(u - ref).max() <= 1e-12 * abs(ref).max()
+        assert abs(u - ref).max() <= 1e-12 * abs(ref).max(), (local, lanes, one)
     ls = LevelSmoother(mesh, deg, omega=om, coef=field, local="half")
     nb, nd = ls.interior[-1].shape
     r = np.random.default_rng(0).uniform(-1, 1, nb * nd)
     d = np.zeros_like(r)
     assert emu.pmgemu_metric_smooth(dim, n, p, ci(deg), len(deg), cd(om), 0, 1, 1, P(V) if V is not None else None,
-                                    carr, None, None, nb, P(r), P(d)) == 0
+                                    carr, None, None, nb, P(r), P(d), 1, 0) == 0
     for j in range(nb):
         ref = ls.local_solve(j, r[j * nd:(j + 1) * nd])
         assert abs(d[j * nd:(j + 1) * nd] - ref).max() <= 1e-12 * abs(ref).max()
