@@ -209,6 +209,24 @@ int pmg_coarse_solve(pmg_problem *pr, int prec, const void *r, void *z, void *st
  * stays float64). */
 int pmg_vcycle(pmg_problem *pr, int mg_prec, const double *r, double *z, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): pmg_vcycle with every work buffer of
+ * the cycle (per-level residuals, corrections and residual products, the intermediates of
+ * the transfer passes, the coarse solve's work vectors and, for FP32 multigrid, the float32
+ * copies of r and z) taken from one static device array of PMG_NOALLOC_SCRATCH_BYTES per GPU
+ * instead of the problem's buffers.  The call allocates nothing and computes exactly what
+ * pmg_vcycle computes (the same kernels in the same order).
+ *   - The problem must be device-initialized and its device current; problems whose
+ *     kernels need a global-memory workgroup arena are UNSUPPORTED.
+ *   - INVALID_ARG, before anything is enqueued, when the cycle needs more work memory than
+ *     the array holds (e.g. 3D Q4 fits up to 32^3 cells in FP64).
+ *   - Every call on a GPU uses that GPU's one array, which keeps the last call's contents
+ *     (every buffer is written before it is read, so nothing is cleared): calls that may
+ *     overlap on one GPU (other streams, other threads) race and must be serialized by the
+ *     caller. */
+#define PMG_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int pmg_vcycle_noalloc(pmg_problem *pr, int mg_prec, const double *r, double *z, void *stream);
+
 /* Flexible CG (float64 vectors, dot products and updates) preconditioned by pmg_vcycle
  * in mg_prec, until |b - A x|_2 <= rtol |b|_2 or max_iter.  Synchronizes the stream once
  * per iteration for the convergence test.  Returns PMG_ERR_NOT_CONVERGED or

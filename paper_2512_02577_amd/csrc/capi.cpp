@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -27,6 +28,41 @@ using namespace pmg;
 namespace {
 
 thread_local std::string g_err;
+
+}  // namespace
+
+// Work memory of pmg_vcycle_noalloc: one copy of this array on every GPU the library runs
+// on, held until the process ends.  Host code never uses its name as an address (on the
+// host it is only a stand-in for the symbol): the per-device address comes from
+// hipGetSymbolAddress in resolve_scratch.
+static __device__ __align__(256) unsigned char scratch[PMG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Resolves the current device's address of `scratch` once per device (called by
+// pmg_device_init, with the problem's device current).
+int resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(PMG_ERR_UNSUPPORTED, "device index %d beyond the %d the library tracks", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return PMG_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(PMG_ERR_DEVICE, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+  g_scratch_ptr[device] = static_cast<char *>(ptr);
+  return PMG_OK;
+}
+
+char *scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -258,8 +294,36 @@ int do_smooth(pmg_problem *pr, int l, int dir, T *u, const T *b, hipStream_t s, 
   return PMG_OK;
 }
 
+// Work buffers of one V-cycle in precision T (r, z on levels below the finest, t on every
+// level above the coarsest, the intermediates of the 1D transfer passes and the coarse
+// solve's work vectors): the problem's own, or carved out of the static scratch array.
 template <typename T>
-int do_restrict(pmg_problem *pr, int l, const T *fine, T *coarse, hipStream_t s, T *zero = nullptr) {
+struct VWork {
+  static constexpr int kMaxLevels = 16;
+  T *r[kMaxLevels] = {}, *z[kMaxLevels] = {}, *t[kMaxLevels] = {};
+  T *tw1 = nullptr, *tw2 = nullptr;
+  double *cw1 = nullptr, *cw2 = nullptr, *cwork = nullptr;
+};
+
+template <typename T>
+VWork<T> own_work(pmg_problem *pr) {
+  VWork<T> w;
+  PrecData<T> &d = pr->pd<T>();
+  for (size_t l = 0; l < pr->sizes.size(); ++l) {
+    w.r[l] = d.r[l];
+    w.z[l] = d.z[l];
+    w.t[l] = d.t[l];
+  }
+  w.tw1 = d.tw1;
+  w.tw2 = d.tw2;
+  w.cw1 = pr->cw1;
+  w.cw2 = pr->cw2;
+  w.cwork = pr->cwork;
+  return w;
+}
+
+template <typename T>
+int do_restrict(pmg_problem *pr, int l, const T *fine, T *coarse, hipStream_t s, T *zero, T *tw1, T *tw2) {
   TransferArgs<T> a{};
   a.zero = zero;
   a.W1 = pr->pd<T>().tabs.W1;
@@ -267,30 +331,30 @@ int do_restrict(pmg_problem *pr, int l, const T *fine, T *coarse, hipStream_t s,
   a.nc = pr->sizes[l - 1];
   a.in = fine;
   a.out = coarse;
-  a.w1 = pr->pd<T>().tw1;
-  a.w2 = pr->pd<T>().tw2;
+  a.w1 = tw1;
+  a.w2 = tw2;
   PMG_TRY(launch_restrict<T>(pr->dim, pr->p, a, s));
   return PMG_OK;
 }
 
 template <typename T>
-int do_prolong(pmg_problem *pr, int l, const T *coarse, T *fine, hipStream_t s) {
+int do_prolong(pmg_problem *pr, int l, const T *coarse, T *fine, hipStream_t s, T *tw1, T *tw2) {
   TransferArgs<T> a{};
   a.W1 = pr->pd<T>().tabs.W1;
   a.Wr = pr->pd<T>().tabs.Wr;
   a.nc = pr->sizes[l - 1];
   a.in = coarse;
   a.out = fine;
-  a.w1 = pr->pd<T>().tw1;
-  a.w2 = pr->pd<T>().tw2;
+  a.w1 = tw1;
+  a.w2 = tw2;
   PMG_TRY(launch_prolong_add<T>(pr->dim, pr->p, a, s));
   return PMG_OK;
 }
 
 template <typename T>
-int do_coarse(pmg_problem *pr, const T *r, T *z, hipStream_t s) {
+int do_coarse(pmg_problem *pr, const T *r, T *z, hipStream_t s, const VWork<T> &w) {
   if (pr->general) {
-    PMG_TRY(launch_coarse_dense<T>(pr->dim, pr->coarse_mi, pr->coarse_mi + 2, pr->Ainv, r, z, pr->cwork, s));
+    PMG_TRY(launch_coarse_dense<T>(pr->dim, pr->coarse_mi, pr->coarse_mi + 2, pr->Ainv, r, z, w.cwork, s));
     return PMG_OK;
   }
   CoarseArgs<T> a{};
@@ -301,18 +365,17 @@ int do_coarse(pmg_problem *pr, const T *r, T *z, hipStream_t s) {
   a.mt = pr->tab.m0 + 2;
   a.r = r;
   a.z = z;
-  a.w1 = pr->cw1;
-  a.w2 = pr->cw2;
+  a.w1 = w.cw1;
+  a.w2 = w.cw2;
   PMG_TRY(launch_coarse<T>(pr->dim, a, s));
   return PMG_OK;
 }
 
 // h-multigrid V(n_pre, n_post) from a zero guess on the finest level (Sec. 2).
 template <typename T>
-int do_vcycle(pmg_problem *pr, const T *r, T *z, hipStream_t s, int store = ST_NATIVE) {
+int do_vcycle(pmg_problem *pr, const VWork<T> &w, const T *r, T *z, hipStream_t s, int store = ST_NATIVE) {
   const int L = pr->finest();
-  PrecData<T> &w = pr->pd<T>();
-  if (L == 0) return do_coarse<T>(pr, r, z, s);
+  if (L == 0) return do_coarse<T>(pr, r, z, s, w);
   for (int l = L; l >= 1; --l) {
     const T *R = l == L ? r : w.r[l];
     T *Z = l == L ? z : w.z[l];
@@ -325,15 +388,15 @@ int do_vcycle(pmg_problem *pr, const T *r, T *z, hipStream_t s, int store = ST_N
     }
     int rc = do_apply<T>(pr, l, true, R, Z, w.t[l], s, store);
     if (rc) return rc;
-    rc = do_restrict<T>(pr, l, w.t[l], w.r[l - 1], s, l - 1 >= 1 ? w.z[l - 1] : nullptr);
+    rc = do_restrict<T>(pr, l, w.t[l], w.r[l - 1], s, l - 1 >= 1 ? w.z[l - 1] : nullptr, w.tw1, w.tw2);
     if (rc) return rc;
   }
-  int rc = do_coarse<T>(pr, w.r[0], w.z[0], s);
+  int rc = do_coarse<T>(pr, w.r[0], w.z[0], s, w);
   if (rc) return rc;
   for (int l = 1; l <= L; ++l) {
     const T *R = l == L ? r : w.r[l];
     T *Z = l == L ? z : w.z[l];
-    rc = do_prolong<T>(pr, l, w.z[l - 1], Z, s);
+    rc = do_prolong<T>(pr, l, w.z[l - 1], Z, s, w.tw1, w.tw2);
     if (rc) return rc;
     for (int k = 0; k < pr->cfg.n_post; ++k) {
       rc = do_smooth<T>(pr, l, -1, Z, R, s, store);
@@ -343,15 +406,73 @@ int do_vcycle(pmg_problem *pr, const T *r, T *z, hipStream_t s, int store = ST_N
   return PMG_OK;
 }
 
-int vcycle_any(pmg_problem *pr, int mg_prec, const double *r, double *z, hipStream_t s) {
-  if (mg_prec == PMG_FP64) return do_vcycle<double>(pr, r, z, s);
-  const int L = pr->finest();
-  const long N = pr->nodes(L);
-  PMG_TRY(launch_cast_d2f(r, pr->d32.r[L], N, s));
-  int rc = do_vcycle<float>(pr, pr->d32.r[L], pr->d32.z[L], s, mg_prec == PMG_FP32_BF16 ? ST_BF16 : ST_NATIVE);
+// z = V(r) in mg_prec with the given work sets; the FP32 cycle takes its copies of r and z
+// on the finest level from r32/z32.
+int vcycle_with(pmg_problem *pr, int mg_prec, const double *r, double *z, hipStream_t s, const VWork<double> &w64,
+                const VWork<float> &w32, float *r32, float *z32) {
+  if (mg_prec == PMG_FP64) return do_vcycle<double>(pr, w64, r, z, s);
+  const long N = pr->nodes(pr->finest());
+  PMG_TRY(launch_cast_d2f(r, r32, N, s));
+  int rc = do_vcycle<float>(pr, w32, r32, z32, s, mg_prec == PMG_FP32_BF16 ? ST_BF16 : ST_NATIVE);
   if (rc) return rc;
-  PMG_TRY(launch_cast_f2d(pr->d32.z[L], z, N, s));
+  PMG_TRY(launch_cast_f2d(z32, z, N, s));
   return PMG_OK;
+}
+
+int vcycle_any(pmg_problem *pr, int mg_prec, const double *r, double *z, hipStream_t s) {
+  const int L = pr->finest();
+  return vcycle_with(pr, mg_prec, r, z, s, own_work<double>(pr), own_work<float>(pr), pr->d32.r[L], pr->d32.z[L]);
+}
+
+// Lays the work set of one V-cycle in precision T out from byte offset `off` of `base`
+// (256-byte aligned pieces); with base == nullptr only the offsets are computed.  Returns
+// the end offset.
+template <typename T>
+size_t carve_work(pmg_problem *pr, char *base, size_t off, VWork<T> &w) {
+  auto take = [&](size_t bytes) -> char * {
+    off = (off + 255) / 256 * 256;
+    char *ptr = base ? base + off : nullptr;
+    off += bytes;
+    return ptr;
+  };
+  const int L = pr->finest();
+  for (int l = 0; l <= L; ++l) {
+    const size_t N = (size_t)pr->nodes(l);
+    if (l < L) {
+      w.r[l] = (T *)take(N * sizeof(T));
+      w.z[l] = (T *)take(N * sizeof(T));
+    }
+    if (l >= 1) w.t[l] = (T *)take(N * sizeof(T));
+  }
+  if (L >= 1) {
+    const size_t mf = (size_t)pr->p * pr->sizes[L] + 1, mc = (size_t)pr->p * pr->sizes[L - 1] + 1;
+    const size_t tw = pr->dim == 3 ? mf * mf * mc : mf * mc;
+    w.tw1 = (T *)take(tw * sizeof(T));
+    w.tw2 = (T *)take(tw * sizeof(T));
+  }
+  if (pr->general) {
+    const size_t mi = (size_t)pr->coarse_mi;
+    w.cwork = (double *)take((pr->dim == 3 ? mi * mi * mi : mi * mi) * sizeof(double));
+  } else {
+    const size_t m0 = (size_t)pr->tab.m0, m0d = pr->dim == 3 ? m0 * m0 * m0 : m0 * m0;
+    w.cw1 = (double *)take(m0d * sizeof(double));
+    w.cw2 = (double *)take(m0d * sizeof(double));
+  }
+  return off;
+}
+
+// Byte layout of pmg_vcycle_noalloc's work memory in mg_prec (base == nullptr: sizes only).
+size_t noalloc_layout(pmg_problem *pr, int mg_prec, char *base, VWork<double> &w64, VWork<float> &w32, float **r32,
+                      float **z32) {
+  if (mg_prec == PMG_FP64) return carve_work<double>(pr, base, 0, w64);
+  const size_t N = (size_t)pr->nodes(pr->finest());
+  size_t off = carve_work<float>(pr, base, 0, w32);
+  off = (off + 255) / 256 * 256;
+  *r32 = base ? (float *)(base + off) : nullptr;
+  off += N * sizeof(float);
+  off = (off + 255) / 256 * 256;
+  *z32 = base ? (float *)(base + off) : nullptr;
+  return off + N * sizeof(float);
 }
 
 template <typename T>
@@ -733,6 +854,7 @@ int pmg_device_init(pmg_problem *pr) {
   int lds = 0, ncu = 0;
   PMG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pr->device));
   PMG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pr->device));
+  if (int rc = resolve_scratch(pr->device)) return rc;
   pr->arena.lds_max = (size_t)lds;
   pr->arena.ncu = ncu > 0 ? ncu : 256;
   pr->arena.patch_lanes = pr->cfg.patch_lanes;
@@ -892,8 +1014,9 @@ int pmg_restrict(pmg_problem *pr, int hlevel, int prec, const void *fine, void *
   if (hlevel < 1) return fail(PMG_ERR_INVALID_ARG, "restriction needs hlevel >= 1");
   if (!fine || !coarse) return fail(PMG_ERR_INVALID_ARG, "fine or coarse is NULL");
   hipStream_t s = (hipStream_t)stream;
-  if (prec == PMG_FP64) return do_restrict<double>(pr, hlevel, (const double *)fine, (double *)coarse, s);
-  return do_restrict<float>(pr, hlevel, (const float *)fine, (float *)coarse, s);
+  if (prec == PMG_FP64)
+    return do_restrict<double>(pr, hlevel, (const double *)fine, (double *)coarse, s, nullptr, pr->d64.tw1, pr->d64.tw2);
+  return do_restrict<float>(pr, hlevel, (const float *)fine, (float *)coarse, s, nullptr, pr->d32.tw1, pr->d32.tw2);
 }
 
 int pmg_prolongate_add(pmg_problem *pr, int hlevel, int prec, const void *coarse, void *fine, void *stream) {
@@ -903,8 +1026,9 @@ int pmg_prolongate_add(pmg_problem *pr, int hlevel, int prec, const void *coarse
   if (hlevel < 1) return fail(PMG_ERR_INVALID_ARG, "prolongation needs hlevel >= 1");
   if (!fine || !coarse) return fail(PMG_ERR_INVALID_ARG, "fine or coarse is NULL");
   hipStream_t s = (hipStream_t)stream;
-  if (prec == PMG_FP64) return do_prolong<double>(pr, hlevel, (const double *)coarse, (double *)fine, s);
-  return do_prolong<float>(pr, hlevel, (const float *)coarse, (float *)fine, s);
+  if (prec == PMG_FP64)
+    return do_prolong<double>(pr, hlevel, (const double *)coarse, (double *)fine, s, pr->d64.tw1, pr->d64.tw2);
+  return do_prolong<float>(pr, hlevel, (const float *)coarse, (float *)fine, s, pr->d32.tw1, pr->d32.tw2);
 }
 
 int pmg_coarse_solve(pmg_problem *pr, int prec, const void *r, void *z, void *stream) {
@@ -912,8 +1036,8 @@ int pmg_coarse_solve(pmg_problem *pr, int prec, const void *r, void *z, void *st
   if (int rc = check_prec(prec)) return rc;
   if (!r || !z) return fail(PMG_ERR_INVALID_ARG, "r or z is NULL");
   hipStream_t s = (hipStream_t)stream;
-  if (prec == PMG_FP64) return do_coarse<double>(pr, (const double *)r, (double *)z, s);
-  return do_coarse<float>(pr, (const float *)r, (float *)z, s);
+  if (prec == PMG_FP64) return do_coarse<double>(pr, (const double *)r, (double *)z, s, own_work<double>(pr));
+  return do_coarse<float>(pr, (const float *)r, (float *)z, s, own_work<float>(pr));
 }
 
 int pmg_vcycle(pmg_problem *pr, int mg_prec, const double *r, double *z, void *stream) {
@@ -921,6 +1045,29 @@ int pmg_vcycle(pmg_problem *pr, int mg_prec, const double *r, double *z, void *s
   if (int rc = check_prec(mg_prec)) return rc;
   if (!r || !z) return fail(PMG_ERR_INVALID_ARG, "r or z is NULL");
   return vcycle_any(pr, mg_prec, r, z, (hipStream_t)stream);
+}
+
+int pmg_vcycle_noalloc(pmg_problem *pr, int mg_prec, const double *r, double *z, void *stream) {
+  if (int rc = check_ready(pr)) return rc;
+  if (int rc = check_prec(mg_prec)) return rc;
+  if (!r || !z) return fail(PMG_ERR_INVALID_ARG, "r or z is NULL");
+  if (pr->arena.global)
+    return fail(PMG_ERR_UNSUPPORTED, "this problem's kernels need a workgroup arena in global memory");
+  int device = -1;
+  PMG_HIP(hipGetDevice(&device));
+  if (device != pr->device)
+    return fail(PMG_ERR_INVALID_ARG, "the problem lives on device %d but device %d is current", pr->device, device);
+  char *base = scratch_of(device);
+  if (!base) return fail(PMG_ERR_STATE, "the scratch array of device %d is not resolved", device);
+  VWork<double> w64;
+  VWork<float> w32;
+  float *r32 = nullptr, *z32 = nullptr;
+  const size_t need = noalloc_layout(pr, mg_prec, nullptr, w64, w32, &r32, &z32);
+  if (need > (size_t)PMG_NOALLOC_SCRATCH_BYTES)
+    return fail(PMG_ERR_INVALID_ARG, "the V-cycle needs %zu bytes of work memory, above the %zu of the scratch array",
+                need, (size_t)PMG_NOALLOC_SCRATCH_BYTES);
+  noalloc_layout(pr, mg_prec, base, w64, w32, &r32, &z32);
+  return vcycle_with(pr, mg_prec, r, z, (hipStream_t)stream, w64, w32, r32, z32);
 }
 
 int pmg_solve(pmg_problem *pr, int mg_prec, const double *b, double *x, int x_is_initial_guess, pmg_solve_info *info,

@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
             "pmg_prolongate_add": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp]),
             "pmg_coarse_solve": (_ip, [_vp, _ip, _vp, _vp, _vp]),
             "pmg_vcycle": (_ip, [_vp, _ip, _vp, _vp, _vp]),
+            "pmg_vcycle_noalloc": (_ip, [_vp, _ip, _vp, _vp, _vp]),
             "pmg_solve": (_ip, [_vp, _ip, _vp, _vp, _ip, P(SolveInfo), _vp]),
             "pmg_destroy_problem": (None, [_vp]),
             "pmg_batch_create": (_ip, [P(_vp), _ip, ctypes.c_char_p, P(_vp)]),
@@ -301,6 +302,17 @@ def vcycle(pr: Problem, r, z, mg_prec: int = FP64) -> None:
 
     n = pr.n_nodes[pr.finest]
     _check(lib().pmg_vcycle(pr.handle, mg_prec, _ptr(r, n, torch.float64), _ptr(z, n, torch.float64), _stream()))
+
+
+def vcycle_noalloc(pr: Problem, r, z, mg_prec: int = FP64) -> None:
+    import torch
+
+    n = pr.n_nodes[pr.finest]
+    _check(lib().pmg_vcycle_noalloc(pr.handle, mg_prec, _ptr(r, n, torch.float64), _ptr(z, n, torch.float64),
+                                    _stream()))
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 
 def solve(pr: Problem, b, x, mg_prec: int = FP64, x_is_initial_guess: bool = False,
