@@ -17,9 +17,13 @@ def test_bench_refuses_more_than_one_gpu():
     assert p.stdout == ""
 
 
-def test_traffic_record_is_well_formed():
-    rec = json.load(open(os.path.join(ROOT, "profiles", "k_smooth_fp64_q4_32cube.traffic.json")))
-    assert rec["fetch_bytes_per_launch"] > 0 and rec["write_bytes_per_launch"] > 0
-    for rel in rec["sources_sha256"]:
-        assert os.path.exists(os.path.join(ROOT, rel)), rel
-    assert os.path.exists(os.path.join(ROOT, rec["summary"]))
+def test_traffic_records_are_well_formed():
+    # the records bench.py reads: HBM bytes per launch of the smoother color launch and of the
+    # apply at 64^3 and 128^3 Q4, each naming its summary and the kernel sources it was taken with
+    for name in ("k_smooth_fp64_q4_64cube", "k_smooth_fp64_q4_128cube", "k_apply_fp64_q4_64cube",
+                 "k_apply_fp64_q4_128cube"):
+        rec = json.load(open(os.path.join(ROOT, "profiles", name + ".traffic.json")))
+        assert rec["fetch_bytes_per_launch"] > 0 and rec["write_bytes_per_launch"] > 0
+        for rel in rec["sources_sha256"]:
+            assert os.path.exists(os.path.join(ROOT, rel)), rel
+        assert os.path.exists(os.path.join(ROOT, rec["summary"]))
