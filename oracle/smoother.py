@@ -10,10 +10,19 @@ of one color by ascending index; the parity coloring makes the result independen
 the order inside a color.
 
 Sec. 2.2, Alg. 2 (LocalSolve, preconditioned Richardson, first step from zero) and
-Alg. 3 (p-V-cycle: damped Jacobi pre-smoothing from zero, residual, restriction by the
-transposed embedding, recursion, prolongation, optional post-smoothing; exact solve on
-the coarsest level, a 1x1 system when its degree is 1).  Patch matrices A_{j,l} are the
-dense extraction of the assembled degree-p_l matrix at the patch interior indices.
+Alg. 3 (p-V-cycle: damped Richardson pre-smoothing from zero, residual, restriction by
+the transposed embedding, recursion, prolongation, optional post-smoothing; exact solve
+on the coarsest level, a 1x1 system when its degree is 1).  Patch matrices A_{j,l} are
+the dense extraction of the assembled degree-p_l matrix at the patch interior indices.
+
+The Richardson preconditioner P_{j,l} of a p-level (Sec. 2.2) is either the diagonal
+(damped Jacobi, the default) or the Cartesian-reinforced one: the inverse of the patch
+operator of the undistorted (Cartesian) mesh, which fast diagonalization applies cheaply,
+combined with diagonal scaling for the actual geometry.  The paper names the
+combination without writing it out; the reading taken here is
+    P^{-1} = D^{-1/2} D_C^{1/2} A_C^{-1} D_C^{1/2} D^{-1/2},
+D = diag(A_{j,l}), A_C the same patch's matrix on the Cartesian mesh with the same cells,
+D_C its diagonal; on a Cartesian mesh P^{-1} = A_{j,l}^{-1}.  Its default damping is 1.
 """
 from __future__ import annotations
 
@@ -38,28 +47,34 @@ class VmultCounter:
 class PatchData:
     """Dense operators of one patch on every p-level."""
 
-    def __init__(self, A, D, P):
+    def __init__(self, A, D, P, AC=None):
         self.A = A  # list over p-levels of dense (n_l, n_l)
         self.D = D  # list of diagonals
         self.P = P  # P[l]: (n_l, n_{l-1}) embedding, P[0] is None
+        self.AC = AC  # Cartesian-reinforced smoother: the patch matrices on the Cartesian mesh
 
 
 class LevelSmoother:
     """Everything the patch smoother needs on one mesh level."""
 
     def __init__(self, mesh: StructuredMesh, degrees: list[int], omega: list[float] | None = None,
-                 coef=None, local: str = "half", n_local_iter: int = 1):
+                 coef=None, local: str = "half", n_local_iter: int = 1, smoother: str = "jacobi"):
         self.mesh = mesh
         self.degrees = list(degrees)
         dim, n = mesh.dim, mesh.n
         self.A = [stiffness_matrix(mesh, q, coef) for q in degrees]
+        if smoother not in ("jacobi", "reinforced"):
+            raise ValueError(smoother)
+        self.smoother = smoother
+        # the reinforced preconditioner's Cartesian patch operators (unit coefficient)
+        self.AC = [stiffness_matrix(StructuredMesh(dim, n), q) for q in degrees] if smoother == "reinforced" else None
         self.interior = [patch_index_sets(dim, n, q)[1] for q in degrees]
         self.closure = patch_index_sets(dim, n, degrees[-1])[0]
         self.P = [None] + [p_prolongation(dim, n, degrees[l - 1], degrees[l]) for l in range(1, len(degrees))]
         self.colors = patch_colors(dim, n)
         self.n_colors = 2 ** dim
         if omega is None:
-            omega = [default_omega(dim, q) for q in degrees]
+            omega = [default_omega(dim, q) if smoother == "jacobi" else 1.0 for q in degrees]
         self.omega = list(omega)
         if local not in ("half", "full", "direct"):
             raise ValueError(local)
@@ -72,25 +87,34 @@ class LevelSmoother:
     def patch(self, j: int) -> PatchData:
         if j in self._cache:
             return self._cache[j]
-        A, D, P = [], [], [None]
+        A, D, P, AC = [], [], [None], []
         for l in range(len(self.degrees)):
             I = self.interior[l][j]
             Al = self.A[l][I][:, I].toarray()
             A.append(Al)
             D.append(np.diag(Al).copy())
+            if self.AC is not None:
+                AC.append(self.AC[l][I][:, I].toarray())
             if l > 0:
                 P.append(self.P[l][I][:, self.interior[l - 1][j]].toarray())
-        pd = PatchData(A, D, P)
+        pd = PatchData(A, D, P, AC if self.AC is not None else None)
         per_patch = sum(a.nbytes for a in A) + sum(x.nbytes for x in P[1:])
         if (len(self._cache) + 1) * per_patch < 2e9:
             self._cache[j] = pd
         return pd
 
+    # ------------------------------------------- Richardson preconditioner P_{j,l}^{-1}
+    def precondition(self, pd: PatchData, l: int, r: np.ndarray) -> np.ndarray:
+        if self.smoother == "jacobi":
+            return r / pd.D[l]
+        s = np.sqrt(np.diag(pd.AC[l]) / pd.D[l])  # D^{-1/2} D_C^{1/2}
+        return s * np.linalg.solve(pd.AC[l], s * r)
+
     # ------------------------------------------------------- Alg. 3: p-V-cycle
     def vcycle(self, pd: PatchData, l: int, r: np.ndarray, full: bool) -> np.ndarray:
         if l == 0:
             return np.linalg.solve(pd.A[0], r)  # 1x1 when the coarsest degree is 1
-        d = self.omega[l] * r / pd.D[l]  # pre-smoothing from a zero guess
+        d = self.omega[l] * self.precondition(pd, l, r)  # pre-smoothing from a zero guess
         res = r - pd.A[l] @ d
         self.counter.count[l] += 1
         rc = pd.P[l].T @ res
@@ -99,7 +123,7 @@ class LevelSmoother:
         if full:
             res = r - pd.A[l] @ d
             self.counter.count[l] += 1
-            d = d + self.omega[l] * res / pd.D[l]
+            d = d + self.omega[l] * self.precondition(pd, l, res)
         return d
 
     # ------------------------------------------------------- Alg. 2: LocalSolve

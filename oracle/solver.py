@@ -28,7 +28,7 @@ class MultigridProblem:
     def __init__(self, dim: int, n: int, p: int, p_levels: list[int] | None = None,
                  vertices: np.ndarray | None = None, coef=None, n_hlevels: int = 0,
                  omega: list[float] | None = None, local: str = "half", n_local_iter: int = 1,
-                 n_pre: int = 1, n_post: int = 1):
+                 n_pre: int = 1, n_post: int = 1, smoother: str = "jacobi"):
         self.dim, self.n, self.p = dim, n, p
         self.degrees = list(p_levels) if p_levels is not None else p_hierarchy(p)
         if self.degrees[-1] != p:
@@ -43,7 +43,7 @@ class MultigridProblem:
             if li == 0:
                 self.levels.append(None)
             else:
-                self.levels.append(LevelSmoother(m, self.degrees, omega, coef, local, n_local_iter))
+                self.levels.append(LevelSmoother(m, self.degrees, omega, coef, local, n_local_iter, smoother))
         from .assembly import stiffness_matrix
 
         self.A = [lv.A[-1] if lv is not None else stiffness_matrix(self.meshes[0], p, coef) for lv in self.levels]
@@ -123,3 +123,55 @@ def fcg(A, b: np.ndarray, precond, rtol: float = 1e-8, max_iter: int = 200, x0: 
 
 def solve(problem: MultigridProblem, b: np.ndarray, rtol: float = 1e-8, max_iter: int = 200):
     return fcg(problem.apply, b, problem.vcycle, rtol, max_iter)
+
+
+def gmres(A, b: np.ndarray, precond, rtol: float = 1e-8, restart: int = 30, max_iter: int = 500):
+    """Restarted GMRES(restart) with right preconditioning, the outer solver the paper uses
+    (Sec. 2.2.1, Table 1): x = x0 + B y, y minimizing |b - A x0 - A B y| over the Krylov
+    space of A B built by Arnoldi with modified Gram-Schmidt; stops when the true residual
+    |b - A x| <= rtol |b| (with right preconditioning the least-squares residual is the true
+    one).  Returns (x, iterations, relative residual history)."""
+    n = len(b)
+    x = np.zeros(n)
+    nb = np.linalg.norm(b)
+    r = b.copy()
+    beta = np.linalg.norm(r)
+    hist = [beta / nb]
+    it = 0
+    while hist[-1] > rtol and it < max_iter:
+        m = min(restart, max_iter - it)
+        V = np.zeros((m + 1, n))
+        Z = np.zeros((m, n))
+        H = np.zeros((m + 1, m))
+        V[0] = r / beta
+        k_done = 0
+        for k in range(m):
+            Z[k] = precond(V[k])
+            w = A(Z[k])
+            for i in range(k + 1):
+                H[i, k] = w @ V[i]
+                w = w - H[i, k] * V[i]
+            H[k + 1, k] = np.linalg.norm(w)
+            if H[k + 1, k] > 0:
+                V[k + 1] = w / H[k + 1, k]
+            k_done = k + 1
+            it += 1
+            e1 = np.zeros(k + 2)
+            e1[0] = beta
+            y, *_ = np.linalg.lstsq(H[:k + 2, :k + 1], e1, rcond=None)
+            res = np.linalg.norm(e1 - H[:k + 2, :k + 1] @ y)
+            hist.append(res / nb)
+            if hist[-1] <= rtol or H[k + 1, k] == 0:
+                break
+        x = x + y @ Z[:k_done]
+        r = b - A(x)
+        beta = np.linalg.norm(r)
+        hist[-1] = beta / nb
+        if H[k_done, k_done - 1] == 0:
+            break
+    return x, it, hist
+
+
+def gmres_solve(problem: MultigridProblem, b: np.ndarray, rtol: float = 1e-8, restart: int = 30,
+                max_iter: int = 500):
+    return gmres(problem.apply, b, problem.vcycle, rtol, restart, max_iter)

@@ -117,3 +117,52 @@ def test_default_omega_in_stable_range(dim, q):
     lam = np.linalg.eigvals(np.diag(1 / pd.D[1]) @ pd.A[1]).real.max()
     assert 0 < w * lam < 2
     np.testing.assert_allclose(w * lam, 4 / 3, rtol=1e-10)
+
+
+# ---- Cartesian-reinforced p-level smoother (Sec. 2.2: fast-diagonalization inverse of the
+# Cartesian patch operator with diagonal scaling) and the exact local solve --------------
+
+@pytest.mark.parametrize("dim,levels", [(2, [1, 3]), (3, [1, 2]), (2, [1, 3, 7])])
+def test_reinforced_half_vcycle_is_exact_on_cartesian_patches(dim, levels):
+    # on a Cartesian mesh the reinforced preconditioner inverts the patch operator, so with
+    # its default damping 1 the first pre-smoothing step already solves the patch problem
+    # and the coarse correction vanishes: one half V-cycle equals the direct solve
+    ls = LevelSmoother(StructuredMesh(dim, 3), levels, local="half", smoother="reinforced")
+    assert ls.omega[1:] == [1.0] * (len(levels) - 1)
+    direct = LevelSmoother(StructuredMesh(dim, 3), levels, local="direct")
+    r = np.random.default_rng(2).uniform(-1, 1, ls.interior[-1].shape[1])
+    for j in (0, 3):
+        A = ls.patch(j).A[-1]
+        d = ls.local_solve(j, r)
+        np.testing.assert_allclose(d, direct.local_solve(j, r), atol=1e-12 * abs(d).max())
+        assert abs(A @ d - r).max() <= 1e-12 * abs(r).max()
+
+
+@pytest.mark.parametrize("dim,p,w", [(2, 3, 0.7), (3, 2, 0.8)])
+def test_reinforced_two_level_closed_form(dim, p, w):
+    # two p-levels {1, p}, damping w, Cartesian: B = w A^{-1} + P A_c^{-1} P^T (I - w I)
+    ls = LevelSmoother(StructuredMesh(dim, 2), [1, p], omega=[1.0, w], local="half", smoother="reinforced")
+    pd = ls.patch(0)
+    A, P, Ac = pd.A[1], pd.P[1], pd.A[0]
+    n = A.shape[0]
+    B = w * np.linalg.inv(A) + (1 - w) * P @ np.linalg.inv(Ac) @ P.T
+    np.testing.assert_allclose(_local_matrix(ls, 0, False), B, atol=1e-12 * abs(B).max())
+
+
+def test_reinforced_preconditioner_on_a_distorted_patch():
+    # the preconditioner matrix P = S^-1 A_C S^-1 (S = D^-1/2 D_C^1/2) keeps the coupling of
+    # the Cartesian patch operator and takes the diagonal of the actual one; it is symmetric
+    # positive definite
+    mesh = StructuredMesh(2, 3, jittered_vertices(2, 3, 0.2, 4))
+    ls = LevelSmoother(mesh, [1, 3], local="half", smoother="reinforced")
+    pd = ls.patch(2)
+    n = pd.A[1].shape[0]
+    Pinv = np.stack([ls.precondition(pd, 1, e) for e in np.eye(n)], axis=1)
+    np.testing.assert_allclose(Pinv, Pinv.T, atol=1e-12 * abs(Pinv).max())
+    Pm = np.linalg.inv(Pinv)
+    np.testing.assert_allclose(np.diag(Pm), pd.D[1], rtol=1e-10)
+    assert np.linalg.eigvalsh(Pm).min() > 0
+    # the Cartesian coupling: P_ij / sqrt(P_ii P_jj) equals that of the Cartesian matrix
+    C = pd.AC[1]
+    np.testing.assert_allclose(Pm / np.sqrt(np.outer(np.diag(Pm), np.diag(Pm))),
+                               C / np.sqrt(np.outer(np.diag(C), np.diag(C))), atol=1e-10)

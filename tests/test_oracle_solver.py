@@ -96,3 +96,49 @@ def test_distorted_variable_coefficient_solve():
     b = rhs_vector(dim, n, p, 4)
     x, it, hist = solve(pb, b)
     assert hist[-1] <= 1e-8 and it < 40
+
+
+def test_gmres_minimal_residual_property():
+    # GMRES step k minimizes |b - A x| over x in span{B b, (A B) B b, ...}: compare with a
+    # least-squares solve over an explicitly built Krylov basis, without restart
+    from oracle.solver import gmres
+
+    rng = np.random.default_rng(3)
+    n = 40
+    A = np.eye(n) * 4 + rng.uniform(-1, 1, (n, n))  # nonsymmetric
+    Bm = np.diag(1 / np.diag(A))
+    b = rng.uniform(-1, 1, n)
+    for k in (1, 3, 7):
+        x, it, hist = gmres(lambda v: A @ v, b, lambda v: Bm @ v, rtol=1e-30, restart=50, max_iter=k)
+        assert it == k
+        K = [Bm @ b]
+        for _ in range(k - 1):
+            K.append(Bm @ (A @ K[-1]))
+        Kb = np.stack(K, axis=1)
+        c, *_ = np.linalg.lstsq(A @ Kb, b, rcond=None)
+        assert abs(np.linalg.norm(b - A @ x) - np.linalg.norm(b - A @ (Kb @ c))) < 1e-10 * np.linalg.norm(b)
+
+
+def test_gmres_exact_in_n_steps_and_restarted_convergence():
+    from oracle.solver import gmres
+
+    rng = np.random.default_rng(4)
+    n = 12
+    A = np.eye(n) * 3 + rng.uniform(-1, 1, (n, n))
+    b = rng.uniform(-1, 1, n)
+    x, it, hist = gmres(lambda v: A @ v, b, lambda v: v, rtol=1e-13, restart=n, max_iter=n)
+    assert it <= n and np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+    assert all(h1 <= h0 * (1 + 1e-12) for h0, h1 in zip(hist[:-1], hist[1:]))
+    x2, it2, _ = gmres(lambda v: A @ v, b, lambda v: v, rtol=1e-10, restart=4, max_iter=400)
+    assert np.linalg.norm(A @ x2 - b) <= 1e-10 * np.linalg.norm(b) and it2 > it
+
+
+def test_gmres_with_vcycle_matches_direct_solution():
+    from oracle.solver import gmres_solve
+
+    pb = MultigridProblem(2, 6, 3)
+    b = rhs_vector(2, 6, 3, 9)
+    x, it, hist = gmres_solve(pb, b, rtol=1e-10)
+    xd = pb.direct_solve(b)
+    assert hist[-1] <= 1e-10 and it < 20
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
