@@ -61,8 +61,17 @@ enum {
 enum { PMG_FP64 = 0, PMG_FP32 = 1, PMG_FP32_BF16 = 2 };
 
 /* Local patch solver (Sec. 2.2): one half V-cycle (no post-smoothing, Sec. 2.2.1) or a
- * full V-cycle per Richardson step. */
-enum { PMG_LOCAL_HALF_V = 0, PMG_LOCAL_FULL_V = 1 };
+ * full V-cycle per Richardson step, or the exact patch solve by fast diagonalization of the
+ * Cartesian patch operator (the comparison solver of Sec. 4.3, Table 3; Cartesian path
+ * only). */
+enum { PMG_LOCAL_HALF_V = 0, PMG_LOCAL_FULL_V = 1, PMG_LOCAL_DIRECT = 2 };
+
+/* Richardson preconditioner of the p-levels inside the local p-multigrid (Sec. 2.2): the
+ * diagonal (damped Jacobi, default damping 4 / (3 lambda_max(D^-1 A))) or the
+ * Cartesian-reinforced one (fast-diagonalization inverse of the Cartesian patch operator
+ * with diagonal scaling; on the Cartesian path it is the inverse of the patch operator,
+ * default damping 1).  Cartesian path only. */
+enum { PMG_SMOOTHER_JACOBI = 0, PMG_SMOOTHER_REINFORCED = 1 };
 
 /* Lanes per patch of the Cartesian smoother launches: by launch size (a color with at
  * most 4 patches per compute unit runs 256 lanes per patch, larger colors the per-degree
@@ -71,7 +80,7 @@ enum { PMG_LOCAL_HALF_V = 0, PMG_LOCAL_FULL_V = 1 };
 enum { PMG_LANES_AUTO = 0, PMG_LANES_NARROW = 1, PMG_LANES_WIDE = 2 };
 
 typedef struct {
-  int local_solver; /* PMG_LOCAL_HALF_V (default) or PMG_LOCAL_FULL_V                  */
+  int local_solver; /* PMG_LOCAL_HALF_V (default), PMG_LOCAL_FULL_V or PMG_LOCAL_DIRECT */
   int n_local_iter; /* Richardson steps of LocalSolve (Alg. 2), >= 1; default 1          */
   int n_pre;        /* smoother applications before the coarse correction, default 1     */
   int n_post;       /* smoother applications after it (descending colors), default 1     */
@@ -80,6 +89,7 @@ typedef struct {
   int n_omega;      /* 0: library damping; else the number of valid entries in omega     */
   double omega[8];  /* Jacobi damping per p-level, coarsest first (entry 0 is unused)    */
   int patch_lanes;  /* PMG_LANES_AUTO (default), PMG_LANES_NARROW or PMG_LANES_WIDE      */
+  int local_smoother; /* PMG_SMOOTHER_JACOBI (default) or PMG_SMOOTHER_REINFORCED       */
 } pmg_config;
 
 typedef struct {

@@ -223,6 +223,9 @@ struct Builder {
       a.n = n;
       a.full = pr->cfg.local_solver == PMG_LOCAL_FULL_V;
       a.n_iter = pr->cfg.n_local_iter;
+      a.direct = pr->cfg.local_solver == PMG_LOCAL_DIRECT;
+      a.reinf = pr->cfg.local_smoother == PMG_SMOOTHER_REINFORCED;
+      for (int q = 0; q < pr->nplev() && q < 4; ++q) a.om.w[q] = (T)pr->tab.omega[q];
       a.u = vec_z<T>(pr, l);
       a.b = vec_r<T>(pr, l);
       a.n_patch = 1;

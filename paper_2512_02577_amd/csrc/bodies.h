@@ -17,6 +17,7 @@ namespace pmg {
 template <typename T>
 struct DevTabs {
   const T *Kp[4], *Mp[4], *invD[4], *Tp[4], *TpT[4];  // per p-level, coarsest first
+  const T *S[4], *ST[4], *Linv[4];                    // fast diagonalization per p-level > 0
   const T *Kr, *Mr;                                   // patch residual (degree p)
   const T *Kt, *Mt;                                   // apply tile (degree p)
   const T *W1, *Wr;                                   // h-embedding
@@ -33,6 +34,13 @@ PMG_INLINE int xcd_remap(int b, int G) {
 // ---------------------------------------------------------------------------------------
 // Vertex-patch smoother (Alg. 1 body for one patch, Alg. 2 local solve, Alg. 3 p-cycle).
 // ---------------------------------------------------------------------------------------
+// Damping per p-level, passed by value (indexed with compile-time levels, so it stays in
+// registers).
+template <typename T>
+struct Omega {
+  T w[4];
+};
+
 template <typename T>
 struct SmoothArgs {
   DevTabs<T> tb;
@@ -43,6 +51,9 @@ struct SmoothArgs {
   int n_patch;       // cnt[0]*cnt[1]*cnt[2]
   int full;          // full V-cycle (post-smoothing) instead of the half V-cycle
   int n_iter;        // Richardson steps of LocalSolve
+  int direct;        // LocalSolve is the exact patch solve (fast diagonalization)
+  int reinf;         // p-level Richardson preconditioner: Cartesian-reinforced, not Jacobi
+  Omega<T> om;       // damping per p-level of the reinforced preconditioner
   T *u;              // solution, updated on patch interiors
   const T *b;        // right-hand side
   // local-solve-only mode (pmg_local_solve): r/d blocks per patch, patch index offset
@@ -171,16 +182,60 @@ struct PatchBody {
     }
   }
 
+  // d = s (S x S x S) diag(Linv) (S x S x S)^T r on p-level l >= 1: fast diagonalization of
+  // the interior patch operator c sum_k K_k (x) M_others (K S = M S diag(lam), S^T M S = I),
+  // its inverse for s = 1/c.  Dense 1D contractions, the first from r into d, the others in
+  // place on d (r and d distinct, ndl(l) entries each).
+  template <int l>
+  PMG_INLINE static void fdm(int tid, const DevTabs<T> &tb, T s, const T *r, T *d) {
+    constexpr int m = nl(l);
+    using Pat = PatDense<m, m>;
+    using D = Dense<m, m>;
+    if constexpr (DIM == 3) {
+      scontract1<0, m, m, m, Pat, NT, false, D, D>(tid, r, d, tb.ST[l]);
+      PMG_SYNC();
+      scontract1<1, m, m, m, Pat, NT, false, D, D, true>(tid, d, d, tb.ST[l]);
+      PMG_SYNC();
+      scontract1<2, m, m, m, Pat, NT, false, D, D, true>(tid, d, d, tb.ST[l]);
+    } else {
+      scontract1<0, m, m, 1, Pat, NT, false, D, D>(tid, r, d, tb.ST[l]);
+      PMG_SYNC();
+      scontract1<1, m, m, 1, Pat, NT, false, D, D, true>(tid, d, d, tb.ST[l]);
+    }
+    PMG_SYNC();
+    const cptr<T> Li = as_const(tb.Linv[l]);
+    for (int e = tid; e < ndl(l); e += NT) d[e] *= s * Li[e];
+    PMG_SYNC();
+    if constexpr (DIM == 3) {
+      scontract1<0, m, m, m, Pat, NT, false, D, D, true>(tid, d, d, tb.S[l]);
+      PMG_SYNC();
+      scontract1<1, m, m, m, Pat, NT, false, D, D, true>(tid, d, d, tb.S[l]);
+      PMG_SYNC();
+      scontract1<2, m, m, m, Pat, NT, false, D, D, true>(tid, d, d, tb.S[l]);
+    } else {
+      scontract1<0, m, m, 1, Pat, NT, false, D, D, true>(tid, d, d, tb.S[l]);
+      PMG_SYNC();
+      scontract1<1, m, m, 1, Pat, NT, false, D, D, true>(tid, d, d, tb.S[l]);
+    }
+  }
+
+  // reinf: the p-level Richardson steps use the Cartesian-reinforced preconditioner (on the
+  // Cartesian path the inverse of the patch operator by fast diagonalization, damped by
+  // om[l]) instead of damped Jacobi
   template <int l>
   PMG_INLINE static void cycle(int tid, T *lds, const DevTabs<T> &tb, T c, T cinv, const T *r, T *d,
-                               bool full, const PreD *pre = nullptr) {
+                               bool full, const PreD *pre = nullptr, bool reinf = false,
+                               Omega<T> om = Omega<T>{}) {
     if constexpr (l == 0) {
       if (tid == 0) d[0] = cinv * as_const(tb.invD[0])[0] * r[0];  // exact 1x1 solve
       PMG_SYNC();
     } else {
       constexpr int q = qd(l), qc = qd(l - 1), m = nl(l), mc = nl(l - 1), ndq = ndl(l);
       const cptr<T> invD = as_const(tb.invD[l]);
-      jacobi<l>(tid, tb, cinv, r, d, pre);  // pre-smoothing d = cinv D^-1 r
+      if (reinf)
+        fdm<l>(tid, tb, cinv * om.w[l], r, d);  // pre-smoothing d = om P^-1 r
+      else
+        jacobi<l>(tid, tb, cinv, r, d, pre);  // pre-smoothing d = cinv D^-1 r
       // on p-level 1 the weights of the one-node coarsest level are read now, so that their
       // loads overlap the residual below
       constexpr int R1 = l == 1 ? (ndq + NT - 1) / NT : 1;
@@ -236,7 +291,7 @@ struct PatchBody {
           scontract1<1, mc, m, 1, PR, NT, false, D, DC>(tid, res, rc, tb.TpT[l]);
         }
         PMG_SYNC();
-        cycle<l - 1>(tid, lds, tb, c, cinv, rc, dc, full, pre);
+        cycle<l - 1>(tid, lds, tb, c, cinv, rc, dc, full, pre, reinf, om);
         if constexpr (DIM == 3) {  // d += P dc
           scontract1<0, mc, mc, mc, PP, NT, false, DC, Dense<m, mc>>(tid, dc, X0, tb.Tp[l]);
           PMG_SYNC();
@@ -253,8 +308,15 @@ struct PatchBody {
       if (full) {  // post-smoothing
         vmult_residual<l>(tid, lds, tb, c, d, r, res);
         PMG_SYNC();
-        lane_gather<ndq, NT, 16, T>(
-            tid, [&](int e) { return invD[e]; }, [&](int e, T x) { d[e] += cinv * x * res[e]; });
+        if (reinf) {
+          T *tmp = res + ndq;  // the vmult's second stage buffer, dead now
+          fdm<l>(tid, tb, cinv * om.w[l], res, tmp);
+          PMG_SYNC();
+          for (int e = tid; e < ndq; e += NT) d[e] += tmp[e];
+        } else {
+          lane_gather<ndq, NT, 16, T>(
+              tid, [&](int e) { return invD[e]; }, [&](int e, T x) { d[e] += cinv * x * res[e]; });
+        }
         PMG_SYNC();
       }
     }
@@ -270,12 +332,19 @@ struct PatchBody {
       cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, false, pre);
       return;
     }
-    const bool full = a.full != 0;
-    cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, full);
+    if constexpr (L >= 2) {
+      if (a.direct) {  // exact patch solve: d = A_j^-1 r
+        fdm<L - 1>(tid, a.tb, a.cinv, r, d);
+        PMG_SYNC();
+        return;
+      }
+    }
+    const bool full = a.full != 0, reinf = a.reinf != 0;
+    cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, full, nullptr, reinf, a.om);
     for (int it = 1; it < a.n_iter; ++it) {
       vmult_residual<L - 1>(tid, lds, a.tb, a.c, it == 1 ? d : cc, r, r);
       PMG_SYNC();
-      cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, cc, full);
+      cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, cc, full, nullptr, reinf, a.om);
       for (int e = tid; e < nd; e += NT) d[e] += cc[e];
       PMG_SYNC();
     }

@@ -79,13 +79,6 @@ struct PatDqp {  // 2NQ x 2NQ block diagonal (also its transpose)
   PMG_HD static constexpr int lo(int r) { return (r / nq) * nq; }
   PMG_HD static constexpr int hi(int r) { return (r / nq) * nq + nq; }
 };
-template <int NO, int NI>
-struct PatDense {
-  static constexpr int nout = NO, nin = NI;
-  PMG_HD static constexpr int lo(int) { return 0; }
-  PMG_HD static constexpr int hi(int) { return NI; }
-};
-
 // out = base - Mat in  along an axis (base may alias out)
 template <int AX, int E0, int E1, int E2, class Pat, int NT, typename T>
 PMG_INLINE void contract_sub(int tid, const T *in, T *out, const T *base, const T *Mat_) {

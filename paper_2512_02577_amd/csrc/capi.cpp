@@ -263,6 +263,9 @@ SmoothArgs<T> smooth_args(pmg_problem *pr, int l) {
   a.n = pr->sizes[l];
   a.full = pr->cfg.local_solver == PMG_LOCAL_FULL_V;
   a.n_iter = pr->cfg.n_local_iter;
+  a.direct = pr->cfg.local_solver == PMG_LOCAL_DIRECT;
+  a.reinf = pr->cfg.local_smoother == PMG_SMOOTHER_REINFORCED;
+  for (int l = 0; l < pr->nplev() && l < 4; ++l) a.om.w[l] = (T)pr->tab.omega[l];
   return a;
 }
 
@@ -649,6 +652,7 @@ void pmg_default_config(pmg_config *cfg) {
   cfg->rtol = 1e-8;
   cfg->n_omega = 0;
   cfg->patch_lanes = PMG_LANES_AUTO;
+  cfg->local_smoother = PMG_SMOOTHER_JACOBI;
 }
 
 int pmg_setup_mesh(int dim, const int32_t *n_cells, int n_hlevels, const double *vertices, pmg_mesh **out) {
@@ -720,8 +724,12 @@ int pmg_setup_dofmap(const pmg_mesh *m, int degree, const int32_t *p_levels, int
   pmg_config c;
   pmg_default_config(&c);
   if (cfg) c = *cfg;
-  if (c.local_solver != PMG_LOCAL_HALF_V && c.local_solver != PMG_LOCAL_FULL_V)
+  if (c.local_solver != PMG_LOCAL_HALF_V && c.local_solver != PMG_LOCAL_FULL_V && c.local_solver != PMG_LOCAL_DIRECT)
     return fail(PMG_ERR_INVALID_ARG, "local_solver unknown");
+  if (c.local_smoother != PMG_SMOOTHER_JACOBI && c.local_smoother != PMG_SMOOTHER_REINFORCED)
+    return fail(PMG_ERR_INVALID_ARG, "local_smoother unknown");
+  if (m->verts.size() && (c.local_solver == PMG_LOCAL_DIRECT || c.local_smoother == PMG_SMOOTHER_REINFORCED))
+    return fail(PMG_ERR_UNSUPPORTED, "fast-diagonalization local solvers need the Cartesian path");
   if (c.n_local_iter < 1 || c.n_local_iter > 64) return fail(PMG_ERR_INVALID_ARG, "n_local_iter must be in [1, 64]");
   if (c.n_pre < 0 || c.n_post < 0 || c.n_pre > 16 || c.n_post > 16)
     return fail(PMG_ERR_INVALID_ARG, "n_pre and n_post must be in [0, 16]");
@@ -744,7 +752,10 @@ int pmg_setup_dofmap(const pmg_mesh *m, int degree, const int32_t *p_levels, int
     pr->degrees = deg;
     pr->cfg = c;
     dvec om;
-    if (c.n_omega > 0) om.assign(c.omega, c.omega + c.n_omega);
+    if (c.n_omega > 0)
+      om.assign(c.omega, c.omega + c.n_omega);
+    else if (c.local_smoother == PMG_SMOOTHER_REINFORCED)
+      om.assign(deg.size(), 1.0);  // the reinforced preconditioner is exact on Cartesian patches
     build_tables(pr->dim, degree, deg, om, pr->sizes[0], pr->tab);
     pr->general = !m->verts.empty();
     for (int l : pr->sizes)
@@ -927,6 +938,8 @@ int pmg_device_init(pmg_problem *pr) {
     return false;
   }();
   if (pr->general && pr->hcode != 0) return bail(fail(PMG_ERR_UNSUPPORTED, "the general path compiles the paper's p-hierarchy only"));
+  if (pr->general && (pr->cfg.local_solver == PMG_LOCAL_DIRECT || pr->cfg.local_smoother == PMG_SMOOTHER_REINFORCED))
+    return bail(fail(PMG_ERR_UNSUPPORTED, "fast-diagonalization local solvers need the Cartesian path"));
   size_t need = 0;
   for (int prec = 0; prec < 2; ++prec) {
     size_t b1 = pr->general ? metric_patch_arena_bytes(pr->dim, prec, pr->p) : patch_arena_bytes(pr->dim, prec, pr->p, pr->hcode);

@@ -266,6 +266,47 @@ void apply_tile_tables(int p, int tc, dvec &Kt, dvec &Mt) {
   Mt = sub(M, NI, p, NO, 0, NI);
 }
 
+// Generalized symmetric eigenproblem K s = lambda M s (M positive definite), m x m row
+// major: eigenvalues lam and eigenvectors as the columns of S (row major), S^T M S = I.
+// Cholesky M = Lc Lc^T, then the symmetric C = Lc^-1 K Lc^-T by cyclic Jacobi, S = Lc^-T Q.
+void gen_eig(int m, const dvec &Ki, const dvec &Mi, dvec &lam, dvec &S) {
+  dvec Lc((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = Mi[(size_t)i * m + j];
+      for (int k = 0; k < j; ++k) s -= Lc[(size_t)i * m + k] * Lc[(size_t)j * m + k];
+      Lc[(size_t)i * m + j] = (i == j) ? std::sqrt(s) : s / Lc[(size_t)j * m + j];
+    }
+  dvec X((size_t)m * m);  // X = Lc^{-1} K
+  for (int c = 0; c < m; ++c)
+    for (int i = 0; i < m; ++i) {
+      double s = Ki[(size_t)i * m + c];
+      for (int k = 0; k < i; ++k) s -= Lc[(size_t)i * m + k] * X[(size_t)k * m + c];
+      X[(size_t)i * m + c] = s / Lc[(size_t)i * m + i];
+    }
+  dvec C((size_t)m * m);  // C = X Lc^{-T}: solve Lc C^T = X^T
+  for (int r = 0; r < m; ++r)
+    for (int i = 0; i < m; ++i) {
+      double s = X[(size_t)r * m + i];
+      for (int k = 0; k < i; ++k) s -= Lc[(size_t)i * m + k] * C[(size_t)r * m + k];
+      C[(size_t)r * m + i] = s / Lc[(size_t)i * m + i];
+    }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < i; ++j) {
+      double s = 0.5 * (C[(size_t)i * m + j] + C[(size_t)j * m + i]);
+      C[(size_t)i * m + j] = C[(size_t)j * m + i] = s;
+    }
+  dvec Qv;
+  sym_eig(m, C, lam, Qv);
+  S.assign((size_t)m * m, 0.0);
+  for (int c = 0; c < m; ++c)
+    for (int i = m - 1; i >= 0; --i) {
+      double s = Qv[(size_t)i * m + c];
+      for (int k = i + 1; k < m; ++k) s -= Lc[(size_t)k * m + i] * S[(size_t)k * m + c];
+      S[(size_t)i * m + c] = s / Lc[(size_t)i * m + i];
+    }
+}
+
 void build_tables(int dim, int p, const std::vector<int> &degrees, const dvec &omega_override,
                   int n_coarse, Tables &t) {
   t = Tables();
@@ -358,51 +399,29 @@ void build_tables(int dim, int p, const std::vector<int> &degrees, const dvec &o
       t.Wr[k] = v;  // class a = 0 (coarse vertex)
     }
   }
+  // fast diagonalization of every p-level's patch operator (exact local solve, and the
+  // Cartesian-reinforced Richardson preconditioner)
+  for (int l = 1; l < L; ++l) {
+    PLevel &P = t.lev[l];
+    gen_eig(P.n, P.Kp, P.Mp, P.lam, P.S);
+    P.ST.assign(P.S.size(), 0.0);
+    for (int i = 0; i < P.n; ++i)
+      for (int a = 0; a < P.n; ++a) P.ST[(size_t)a * P.n + i] = P.S[(size_t)i * P.n + a];
+    size_t N = 1;
+    for (int d = 0; d < dim; ++d) N *= P.n;
+    P.Linv.resize(N);
+    for (size_t I = 0; I < N; ++I) {
+      const int i = (int)(I % P.n), j = (int)((I / P.n) % P.n), k = (int)(I / ((size_t)P.n * P.n));
+      P.Linv[I] = 1.0 / (P.lam[i] + P.lam[j] + (dim == 3 ? P.lam[k] : 0.0));
+    }
+  }
   // coarsest mesh: generalized eigenproblem K s = lambda M s of the 1D interior matrices
   {
     dvec K, M;
     line_matrices(p, n_coarse, K, M);
     int Nl = p * n_coarse + 1, m = Nl - 2;
     t.m0 = m;
-    dvec Ki = sub(K, Nl, 1, m, 1, m), Mi = sub(M, Nl, 1, m, 1, m);
-    // Cholesky M = Lc Lc^T
-    dvec Lc((size_t)m * m, 0.0);
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j <= i; ++j) {
-        double s = Mi[(size_t)i * m + j];
-        for (int k = 0; k < j; ++k) s -= Lc[(size_t)i * m + k] * Lc[(size_t)j * m + k];
-        Lc[(size_t)i * m + j] = (i == j) ? std::sqrt(s) : s / Lc[(size_t)j * m + j];
-      }
-    // C = Lc^{-1} K Lc^{-T}
-    dvec X((size_t)m * m);  // X = Lc^{-1} K
-    for (int c = 0; c < m; ++c)
-      for (int i = 0; i < m; ++i) {
-        double s = Ki[(size_t)i * m + c];
-        for (int k = 0; k < i; ++k) s -= Lc[(size_t)i * m + k] * X[(size_t)k * m + c];
-        X[(size_t)i * m + c] = s / Lc[(size_t)i * m + i];
-      }
-    dvec C((size_t)m * m);  // C = X Lc^{-T}: solve Lc C^T = X^T
-    for (int r = 0; r < m; ++r)
-      for (int i = 0; i < m; ++i) {
-        double s = X[(size_t)r * m + i];
-        for (int k = 0; k < i; ++k) s -= Lc[(size_t)i * m + k] * C[(size_t)r * m + k];
-        C[(size_t)r * m + i] = s / Lc[(size_t)i * m + i];
-      }
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < i; ++j) {
-        double s = 0.5 * (C[(size_t)i * m + j] + C[(size_t)j * m + i]);
-        C[(size_t)i * m + j] = C[(size_t)j * m + i] = s;
-      }
-    dvec Qv;
-    sym_eig(m, C, t.lam0, Qv);
-    // S = Lc^{-T} Q
-    t.S0.assign((size_t)m * m, 0.0);
-    for (int c = 0; c < m; ++c)
-      for (int i = m - 1; i >= 0; --i) {
-        double s = Qv[(size_t)i * m + c];
-        for (int k = i + 1; k < m; ++k) s -= Lc[(size_t)k * m + i] * t.S0[(size_t)k * m + c];
-        t.S0[(size_t)i * m + c] = s / Lc[(size_t)i * m + i];
-      }
+    gen_eig(m, sub(K, Nl, 1, m, 1, m), sub(M, Nl, 1, m, 1, m), t.lam0, t.S0);
   }
 }
 

@@ -36,6 +36,10 @@ struct PLevel {
   dvec invD;          // n^dim: omega / Dref (level > 0) or 1 / Dref (level 0)
   dvec Tp;            // n x n_coarse embedding from the next coarser p-level (level > 0)
   dvec TpT;           // its transpose, n_coarse x n
+  // fast diagonalization of the interior patch operator (level > 0): K S = M S diag(lam),
+  // S^T M S = I; S and ST = S^T row major (n x n); Linv = 1 / (lam_i + lam_j (+ lam_k)),
+  // n^dim, so that the patch operator's inverse is (S x S x S) diag(Linv) (S x S x S)^T / c
+  dvec S, ST, lam, Linv;
 };
 
 struct Tables {
@@ -60,6 +64,10 @@ void apply_tile_tables(int p, int tc, dvec &Kt, dvec &Mt);
 // omega_override: empty for the default 4 / (3 lambda_max(D^{-1} A)) per level.
 void build_tables(int dim, int p, const std::vector<int> &degrees, const dvec &omega_override,
                   int n_coarse, Tables &t);
+
+// K s = lambda M s for symmetric K and positive definite M (m x m, row major): eigenvalues
+// and the eigenvectors as columns of S, normalized to S^T M S = I.
+void gen_eig(int m, const dvec &K, const dvec &M, dvec &lam, dvec &S);
 
 // lambda_max of D^{-1} A on the reference interior patch operator at one level.
 double patch_lambda_max(int dim, const PLevel &L);

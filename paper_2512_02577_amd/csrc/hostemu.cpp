@@ -107,6 +107,9 @@ struct HostTabs {
       d.invD[l] = t.lev[l].invD.data();
       d.Tp[l] = t.lev[l].Tp.empty() ? nullptr : t.lev[l].Tp.data();
       d.TpT[l] = t.lev[l].TpT.empty() ? nullptr : t.lev[l].TpT.data();
+      d.S[l] = t.lev[l].S.empty() ? nullptr : t.lev[l].S.data();
+      d.ST[l] = t.lev[l].ST.empty() ? nullptr : t.lev[l].ST.data();
+      d.Linv[l] = t.lev[l].Linv.empty() ? nullptr : t.lev[l].Linv.data();
     }
     d.Kr = t.Kr.data();
     d.Mr = t.Mr.data();
@@ -169,7 +172,8 @@ struct EmuSmooth {
     static int run(const SmoothArgs<double> &base, int n, int color_dir, bool local_only, int n_blocks, int lanes,
                    int one) {
       const bool o = one != 0;
-      if (o && (base.full || base.n_iter != 1)) return -3;  // ONE compiles the default solver only
+      if (o && (base.full || base.n_iter != 1 || base.direct || base.reinf))
+        return -3;  // ONE compiles the default solver only
       switch (lanes) {
         case 0: return o ? go<1, true>(base, n, color_dir, local_only, n_blocks)
                          : go<1, false>(base, n, color_dir, local_only, n_blocks);
@@ -327,6 +331,15 @@ void emu_inv_diag(int n, int q, double omega, const dvec &G, dvec &invD) {
   for (long tt = 0; tt < np * nd; ++tt) patch_inv_diag<DIM, double>(tt, q, n, omega, cd.data(), invD.data());
 }
 
+// Cartesian patch-solver arguments: local 0 half V-cycle, 1 full V-cycle, 2 exact solve;
+// reinf: Cartesian-reinforced p-level preconditioner (damping omega) instead of Jacobi
+void set_local(SmoothArgs<double> &a, const HostTabs &h, int local, int reinf) {
+  a.full = local == 1;
+  a.direct = local == 2;
+  a.reinf = reinf;
+  for (size_t l = 0; l < h.t.lev.size() && l < 4; ++l) a.om.w[l] = h.t.omega[l];
+}
+
 }  // namespace
 
 extern "C" {
@@ -396,8 +409,8 @@ int pmgemu_metric_smooth(int dim, int n, int p, const int *deg, int L, const dou
 }
 
 // One smoother application (all colors) on a single Cartesian level of n^dim cells.
-int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
-                  int color_dir, double *u, const double *b, int lanes, int one, int tabmode) {
+int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int local, int reinf,
+                  int n_iter, int color_dir, double *u, const double *b, int lanes, int one, int tabmode) {
   HostTabs h;
   make_tabs(h, dim, p, deg, L, omega, n, tabmode);
   SmoothArgs<double> a{};
@@ -405,7 +418,7 @@ int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *om
   a.c = cscale(dim, n);
   a.cinv = 1.0 / a.c;
   a.n = n;
-  a.full = full;
+  set_local(a, h, local, reinf);
   a.n_iter = n_iter;
   a.u = u;
   a.b = b;
@@ -415,8 +428,8 @@ int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *om
   return dispatch_hierarchy<EmuSmooth<2>::F>(p, code, a, n, color_dir, false, 0, lanes, one);
 }
 
-int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
-                       int n_blocks, const double *r, double *d, int lanes, int tabmode) {
+int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const double *omega, int local, int reinf,
+                       int n_iter, int n_blocks, const double *r, double *d, int lanes, int tabmode) {
   HostTabs h;
   make_tabs(h, dim, p, deg, L, omega, n, tabmode);
   SmoothArgs<double> a{};
@@ -424,7 +437,7 @@ int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const doubl
   a.c = cscale(dim, n);
   a.cinv = 1.0 / a.c;
   a.n = n;
-  a.full = full;
+  set_local(a, h, local, reinf);
   a.n_iter = n_iter;
   a.r_blocks = r;
   a.d_blocks = d;

@@ -14,10 +14,10 @@
 #include <vector>
 
 extern "C" {
-int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
-                  int color_dir, double *u, const double *b, int lanes, int one, int tabmode);
-int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const double *omega, int full, int n_iter,
-                       int n_blocks, const double *r, double *d, int lanes, int tabmode);
+int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *omega, int local, int reinf,
+                  int n_iter, int color_dir, double *u, const double *b, int lanes, int one, int tabmode);
+int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const double *omega, int local, int reinf,
+                       int n_iter, int n_blocks, const double *r, double *d, int lanes, int tabmode);
 int pmgemu_apply(int dim, int n, int p, int resid, const double *u, const double *b, double *out, int lanes);
 int pmgemu_transfer(int dim, int nc, int p, int restrict_, const double *in, double *out);
 int pmgemu_coarse_solve(int dim, int n0, int p, const double *r, double *z, int lanes);
@@ -70,25 +70,29 @@ int main(int argc, char **argv) {
             // one Richardson step uses the smaller arena: check both sizes; the default local
             // solver also runs in its own compiled variant (one = 1)
             for (int it = 1; it <= 2; ++it)
-              for (int full = 0; full < 2; ++full) {
-                check(pmgemu_smooth(dim, n, p, deg.data(), L, om.data(), full, it, 1, u.data(), b.data(), lanes, 0,
-                                    lanes % 2),
-                      "smooth", dim, p, n, lanes);
-                if (it == 1 && full == 0)
-                  for (int tabmode = 0; tabmode < 2; ++tabmode)
-                    check(pmgemu_smooth(dim, n, p, deg.data(), L, om.data(), 0, 1, -1, u.data(), b.data(), lanes, 1,
-                                        tabmode),
-                          "smooth one", dim, p, n, lanes);
-              }
+              for (int full = 0; full < 2; ++full)
+                for (int reinf = 0; reinf < 2; ++reinf) {
+                  check(pmgemu_smooth(dim, n, p, deg.data(), L, om.data(), full, reinf, it, 1, u.data(), b.data(),
+                                      lanes, 0, lanes % 2),
+                        "smooth", dim, p, n, lanes);
+                  if (it == 1 && full == 0 && reinf == 0)
+                    for (int tabmode = 0; tabmode < 2; ++tabmode)
+                      check(pmgemu_smooth(dim, n, p, deg.data(), L, om.data(), 0, 0, 1, -1, u.data(), b.data(), lanes,
+                                          1, tabmode),
+                            "smooth one", dim, p, n, lanes);
+                }
+            check(pmgemu_smooth(dim, n, p, deg.data(), L, om.data(), 2, 0, 1, 1, u.data(), b.data(), lanes, 0, 1),
+                  "smooth direct", dim, p, n, lanes);
           }
           const long nd = ipow(2 * p - 1, dim), np = ipow(n - 1, dim);
           auto r = rnd(nd * np, 3);
           std::vector<double> d(nd * np);
           for (int lanes = 0; lanes <= 1; ++lanes)
             for (int it = 1; it <= 2; ++it)
-              check(pmgemu_local_solve(dim, n, p, deg.data(), L, om.data(), 0, it, (int)np, r.data(), d.data(), lanes,
-                                       lanes),
-                    "local", dim, p, n, lanes);
+              for (int local = 0; local < 3; ++local)
+                check(pmgemu_local_solve(dim, n, p, deg.data(), L, om.data(), local, it - 1, it, (int)np, r.data(),
+                                         d.data(), lanes, lanes),
+                      "local", dim, p, n, lanes);
           if (code == 0) {
             for (int lanes = 0; lanes <= 1; ++lanes) {
               check(pmgemu_apply(dim, n, p, 1, u.data(), b.data(), out.data(), lanes), "apply", dim, p, n, lanes);

@@ -127,7 +127,7 @@ struct SmoothL {
       static int run(const SmoothArgs<T> &a, const Arena &ar, hipStream_t s) {
         using B = PatchBody<DIM, T, patch_threads(P), P, H>;
         const size_t bytes = B::arena(a.n_iter) * sizeof(T);
-        const bool one = a.full == 0 && a.n_iter == 1;
+        const bool one = a.full == 0 && a.n_iter == 1 && a.direct == 0 && a.reinf == 0;
         // patch_lanes: 0 by launch size, 1 always the per-degree count, 2 always 256
         const bool wide = ar.patch_lanes == 2 || (ar.patch_lanes == 0 && a.n_patch <= kWideLaunch * ar.ncu);
         if constexpr (patch_threads(P) < 256)

@@ -168,6 +168,14 @@ struct PatTile {
   PMG_HD static constexpr int hi(int o) { return P * (o / P + 1) + P + 1; }
 };
 
+// A dense NO x NI matrix (every row touches every column).
+template <int NO, int NI>
+struct PatDense {
+  static constexpr int nout = NO, nin = NI;
+  PMG_HD static constexpr int lo(int) { return 0; }
+  PMG_HD static constexpr int hi(int) { return NI; }
+};
+
 // ---- one output of a 1D contraction on a register pencil ------------------------------
 // Row o of a matrix with sparsity Pat as one FMA chain seeded with its first product: an
 // accumulator started at 0 costs one more instruction (0 + x is not folded away under IEEE

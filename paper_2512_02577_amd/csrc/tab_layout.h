@@ -22,6 +22,9 @@ void bind_tabs(DevTabs<T> &d, const Tables &t, T *base, const std::vector<size_t
     d.invD[l] = base + off[k++];
     d.Tp[l] = base + off[k++];
     d.TpT[l] = base + off[k++];
+    d.S[l] = base + off[k++];
+    d.ST[l] = base + off[k++];
+    d.Linv[l] = base + off[k++];
   }
   d.Kr = base + off[k++];
   d.Mr = base + off[k++];
@@ -44,6 +47,9 @@ inline void flatten_tabs(const Tables &t, std::vector<double> &flat, std::vector
     put(L.invD);
     put(L.Tp);
     put(L.TpT);
+    put(L.S);
+    put(L.ST);
+    put(L.Linv);
   }
   put(t.Kr);
   put(t.Mr);

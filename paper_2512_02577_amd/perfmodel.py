@@ -41,21 +41,34 @@ def kron_flops(dim: int, nin: int, nout: int, nnz: int) -> int:
     return 2 * nnz * (nin + nout)
 
 
-def local_solve_flops(dim: int, degrees: list[int], full: bool = False, n_iter: int = 1) -> int:
+def fdm_flops(dim: int, n: int) -> int:
+    """Fast diagonalization on an n^dim patch tensor: 2 dim dense n x n contractions (each
+    n^(dim+1) multiply-adds) and the eigenvalue scaling."""
+    return 2 * dim * 2 * n ** (dim + 1) + 2 * n**dim
+
+
+def local_solve_flops(dim: int, degrees: list[int], full: bool = False, n_iter: int = 1,
+                      smoother: str = "jacobi", direct: bool = False) -> int:
+    top = len(degrees) - 1
+    if direct:
+        return fdm_flops(dim, 2 * degrees[top] - 1)
+
+    def precond(n):  # one Richardson preconditioner application on an n^dim tensor
+        return 2 * n**dim if smoother == "jacobi" else fdm_flops(dim, n) + n**dim
+
     def cycle(l: int) -> int:
         if l == 0:
             return 2
         q, qc = degrees[l], degrees[l - 1]
         n, nc = 2 * q - 1, 2 * qc - 1
         nd = n**dim
-        f = 2 * nd + laplace_flops(dim, n, n, _nnz_interior(q))
+        f = precond(n) + laplace_flops(dim, n, n, _nnz_interior(q))
         f += kron_flops(dim, n, nc, _nnz_restrict(q, qc)) + kron_flops(dim, nc, n, _nnz_prolong(q, qc))
         f += cycle(l - 1)
         if full:
-            f += laplace_flops(dim, n, n, _nnz_interior(q)) + 3 * nd
+            f += laplace_flops(dim, n, n, _nnz_interior(q)) + precond(n) + nd
         return f
 
-    top = len(degrees) - 1
     n = 2 * degrees[top] - 1
     one = cycle(top)
     extra = laplace_flops(dim, n, n, _nnz_interior(degrees[top])) + one + n**dim

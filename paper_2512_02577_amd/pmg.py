@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libpmg.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 FP64, FP32, FP32_BF16 = 0, 1, 2
-LOCAL_HALF_V, LOCAL_FULL_V = 0, 1
+LOCAL_HALF_V, LOCAL_FULL_V, LOCAL_DIRECT = 0, 1, 2
+SMOOTHER_JACOBI, SMOOTHER_REINFORCED = 0, 1
 LANES_AUTO, LANES_NARROW, LANES_WIDE = 0, 1, 2
 
 
@@ -33,7 +34,8 @@ class PmgError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("local_solver", ctypes.c_int), ("n_local_iter", ctypes.c_int), ("n_pre", ctypes.c_int),
                 ("n_post", ctypes.c_int), ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("n_omega", ctypes.c_int), ("omega", ctypes.c_double * 8), ("patch_lanes", ctypes.c_int)]
+                ("n_omega", ctypes.c_int), ("omega", ctypes.c_double * 8), ("patch_lanes", ctypes.c_int),
+                ("local_smoother", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

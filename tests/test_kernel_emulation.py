@@ -79,8 +79,8 @@ def test_smoother(emu, dim, n, p, lv, local):
         for direction in (1, -1):
             ref = ls.smooth(u0, b, descending=direction < 0)
             u = u0.copy()
-            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), it, direction,
-                                     P(u), P(b), 0, 0, 0) == 0
+            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), 0, it,
+                                     direction, P(u), P(b), 0, 0, 0) == 0
             assert abs(u - ref).max() <= 1e-12 * abs(ref).max()
 
 
@@ -104,8 +104,8 @@ def test_smoother_lane_teams(emu, dim, n, p, lv):
         ref = ls.smooth(u0, b, descending=direction < 0)
         for lanes, one, tabmode in ((1, 1, 1), (2, 1, 0), (1, 0, 0), (2, 0, 1)):
             u = u0.copy()
-            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), 0, 1, direction, P(u), P(b), lanes, one,
-                                     tabmode) == 0
+            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), 0, 0, 1, direction, P(u), P(b), lanes,
+                                     one, tabmode) == 0
             assert abs(u - ref).max() <= 1e-12 * abs(ref).max(), (lanes, one, tabmode, direction)
 
 
@@ -120,8 +120,8 @@ def test_smoother_lane_teams_full_and_richardson(emu, dim, n, p):
         ref = ls.smooth(u0, b)
         for lanes in (1, 2):
             u = u0.copy()
-            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), it, 1, P(u), P(b),
-                                     lanes, 0, 1) == 0
+            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), int(local == "full"), 0, it, 1, P(u),
+                                     P(b), lanes, 0, 1) == 0
             assert abs(u - ref).max() <= 1e-12 * abs(ref).max(), (local, it, lanes)
 
 
@@ -130,7 +130,51 @@ def test_one_variant_rejects_other_solvers(emu):
     om = [1.0, 0.6, 0.6]
     b = rhs_vector(3, 2, 4, 1)
     u = np.zeros_like(b)
-    assert emu.pmgemu_smooth(3, 2, 4, ci(deg), 3, cd(om), 1, 1, 1, P(u), P(b), 1, 1, 0) == -3
+    assert emu.pmgemu_smooth(3, 2, 4, ci(deg), 3, cd(om), 1, 0, 1, 1, P(u), P(b), 1, 1, 0) == -3
+    assert emu.pmgemu_smooth(3, 2, 4, ci(deg), 3, cd(om), 0, 1, 1, 1, P(u), P(b), 1, 1, 0) == -3
+
+
+# exact patch solve (fast diagonalization) and the Cartesian-reinforced p-level smoother
+FDM_CASES = [(2, 4, 3, None), (2, 3, 7, None), (3, 3, 2, None), (3, 3, 4, None), (3, 3, 4, [1, 2, 3, 4]),
+             (3, 2, 5, None), (3, 2, 8, None)]
+
+
+@pytest.mark.parametrize("dim,n,p,lv", FDM_CASES)
+def test_direct_and_reinforced_smoother(emu, dim, n, p, lv):
+    deg = lv or p_hierarchy(p)
+    b = rhs_vector(dim, n, p, 7)
+    u0 = np.random.default_rng(8).uniform(-1, 1, len(b))
+    om_r = [1.0] + [0.8 + 0.05 * l for l in range(1, len(deg))]
+    cases = [("direct", "jacobi", [1.0] * len(deg), 2, 0, 1),
+             ("half", "reinforced", om_r, 0, 1, 1), ("full", "reinforced", om_r, 1, 1, 1),
+             ("half", "reinforced", om_r, 0, 1, 2)]
+    for local, sm, om, code, reinf, it in cases:
+        ls = LevelSmoother(StructuredMesh(dim, n), deg, omega=om, local=local, smoother=sm, n_local_iter=it)
+        for direction, lanes in ((1, 1), (-1, 2), (1, 0)):
+            ref = ls.smooth(u0, b, descending=direction < 0)
+            u = u0.copy()
+            assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), code, reinf, it, direction, P(u), P(b),
+                                     lanes, 0, lanes % 2) == 0
+            assert abs(u - ref).max() <= 1e-12 * abs(ref).max(), (local, sm, it, lanes)
+
+
+@pytest.mark.parametrize("dim,p", [(3, 4), (2, 7)])
+def test_direct_and_reinforced_local_solve(emu, dim, p):
+    deg = p_hierarchy(p)
+    om = [1.0] + [0.9] * (len(deg) - 1)
+    r = None
+    for local, sm, code, reinf in (("direct", "jacobi", 2, 0), ("half", "reinforced", 0, 1),
+                                   ("full", "reinforced", 1, 1)):
+        ls = LevelSmoother(StructuredMesh(dim, 3), deg, omega=om, local=local, smoother=sm)
+        nb, nd = ls.interior[-1].shape
+        if r is None:
+            r = np.random.default_rng(1).uniform(-1, 1, nb * nd)
+        d = np.zeros_like(r)
+        assert emu.pmgemu_local_solve(dim, 3, p, ci(deg), len(deg), cd(om), code, reinf, 1, nb, P(r), P(d), 1,
+                                      1) == 0
+        for j in range(nb):
+            ref = ls.local_solve(j, r[j * nd:(j + 1) * nd])
+            assert abs(d[j * nd:(j + 1) * nd] - ref).max() <= 1e-12 * abs(ref).max(), (local, sm)
 
 
 @pytest.mark.parametrize("dim,p", [(2, 3), (3, 4), (3, 2)])
@@ -144,7 +188,8 @@ def test_local_solve(emu, dim, p):
     d = np.zeros_like(r)
     for lanes in (0, 1):
         d[:] = 0
-        assert emu.pmgemu_local_solve(dim, 3, p, ci(deg), len(deg), cd(om), 0, 1, nb, P(r), P(d), lanes, lanes) == 0
+        assert emu.pmgemu_local_solve(dim, 3, p, ci(deg), len(deg), cd(om), 0, 0, 1, nb, P(r), P(d), lanes,
+                                      lanes) == 0
         for j in range(nb):
             ref = ls.local_solve(j, r[j * nd:(j + 1) * nd])
             assert abs(d[j * nd:(j + 1) * nd] - ref).max() <= 1e-13 * abs(ref).max()
