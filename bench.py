@@ -18,12 +18,16 @@ whole path).  value = nodes x V-cycles / time (DoF/s per V-cycle).  Beside it:
   * the degree sweep p = 2..8 at 64^3 (FP64-MG and FP32-MG time to 1e-8, iterations);
   * 128^3 Q4 (135M nodes, working set far beyond the 256 MB last-level cache): apply and
     smoother rates;
+  * the local solver strategies of the paper's Table 3 (half and full p-V-cycles with Jacobi or
+    Cartesian-reinforced smoothing, the exact fast-diagonalization solve), time and FLOPs per
+    patch relative to the half V-cycle;
   * the 16-problem batch against the same solves one by one;
   * the CPU oracle on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batch] [--no-sweep]
                     [--extras]        (also the 48^3 Q6 perturbed mesh with a coefficient)
     python bench.py --counters       (short kernel runs for rocprofv3 counter passes)
+    python bench.py --table1         (outer iteration counts on the grid of Table 1)
 """
 import argparse
 import json
@@ -262,6 +266,83 @@ def bench_general(torch, pmg, steps):
     return rec
 
 
+# Table 3's local solver strategies (Sec. 4.3), timed per patch in FP64
+LOCAL_SOLVERS = [("half V-cycle (Jacobi)", 0, 0, False, "jacobi"), ("V-cycle (Jacobi)", 1, 0, True, "jacobi"),
+                 ("half V-cycle (Cartesian-reinforced)", 0, 1, False, "reinforced"),
+                 ("V-cycle (Cartesian-reinforced)", 1, 1, True, "reinforced"),
+                 ("fast diagonalization (exact)", 2, 0, False, "jacobi")]
+# the paper's relative times and FLOPs (normalized by the patch operator, p = 7, one CPU core)
+PAPER_TABLE3 = {"half V-cycle (Jacobi)": (2.01, 1.17), "V-cycle (Jacobi)": (3.39, 2.27),
+                "half V-cycle (Cartesian-reinforced)": (4.67, 1.87), "V-cycle (Cartesian-reinforced)": (8.68, 3.67),
+                "fast diagonalization (exact)": (2.60, 0.68)}
+
+
+def bench_local_solvers(torch, pmg, perfmodel, np, reps):
+    """LocalSolve alone (pmg_local_solve) on every patch of the finest level of a 32^3 mesh,
+    FP64, for each local solver strategy of Table 3: time and counted FLOPs relative to the
+    half V-cycle with Jacobi smoothing (the paper's Table 3 divided by its half V-cycle row
+    beside them)."""
+    out = []
+    for p in (4, 7):
+        n = 32
+        log(f"bench: local solvers 32^3 Q{p}")
+        deg = None
+        recs = []
+        for name, loc, sm, full, smn in LOCAL_SOLVERS:
+            cfg = pmg.default_config()
+            cfg.local_solver, cfg.local_smoother = loc, sm
+            pr = pmg.make_problem(3, n, p, config=cfg)
+            deg = pr.degrees
+            nb = pr.n_patches[-1]
+            nd = (2 * p - 1) ** 3
+            r = torch.as_tensor(np.random.default_rng(5).uniform(-1, 1, nb * nd), dtype=torch.float64, device="cuda:0")
+            d = torch.empty_like(r)
+            t = time_events(lambda: pmg.local_solve(pr, pr.finest, r, d), reps, torch)
+            fl = perfmodel.local_solve_flops(3, deg, full=full, smoother=smn, direct=loc == 2) * nb
+            recs.append({"solver": name, "ms": t, "gflops": fl / (t * 1e-3) / 1e9, "flops_per_patch": fl // nb})
+            del pr, r, d
+            torch.cuda.empty_cache()
+        base_t, base_f = recs[0]["ms"], recs[0]["flops_per_patch"]
+        pt = PAPER_TABLE3["half V-cycle (Jacobi)"]
+        for rc in recs:
+            rc["relative_time"] = rc["ms"] / base_t
+            rc["relative_flops"] = rc["flops_per_patch"] / base_f
+            paper = PAPER_TABLE3[rc["solver"]]
+            rc["paper_p7_relative_time"] = paper[0] / pt[0]
+            rc["paper_p7_relative_flops"] = paper[1] / pt[1]
+        out.append({"degree": p, "patches": (n - 1) ** 3, "degrees": deg, "solvers": recs})
+    return out
+
+
+def bench_table1(torch, pmg):
+    """Outer FCG iterations (FP64 multigrid) on the grid of Table 1: local solvers
+    {1 V-cycle, 1 half V-cycle, 2 half V-cycles, 25 V-cycles} x interior-vertex distortion x
+    p in {3, 7}, 2D 32^2 and 3D 16^3 cells (the paper's sizes are not given)."""
+    from paper_2512_02577_amd.inputs import jittered_vertices, rhs_vector
+
+    variants = [("1 V-cycle", pmg.LOCAL_FULL_V, 1), ("1 half V-cycle", pmg.LOCAL_HALF_V, 1),
+                ("2 half V-cycles", pmg.LOCAL_HALF_V, 2), ("25 V-cycles", pmg.LOCAL_FULL_V, 25)]
+    out = []
+    for dim, n, deltas in ((2, 32, (0.0, 0.10, 0.25, 0.35)), (3, 16, (0.0, 0.10, 0.25, 0.30))):
+        for p in (3, 7):
+            for delta in deltas:
+                log(f"bench: table 1 grid {dim}D {n} cells Q{p} distortion {delta}")
+                verts = jittered_vertices(dim, n, delta, 91) if delta > 0 else None
+                b = torch.as_tensor(rhs_vector(dim, n, p, 90), dtype=torch.float64, device="cuda:0")
+                rec = {"dim": dim, "n": n, "p": p, "delta": delta}
+                for name, loc, it in variants:
+                    cfg = pmg.default_config()
+                    cfg.local_solver, cfg.n_local_iter = loc, it
+                    pr = pmg.make_problem(dim, n, p, config=cfg, vertices=verts)
+                    x = torch.empty_like(b)
+                    info = pmg.solve(pr, b, x, pmg.FP64)
+                    rec[name] = info.iterations
+                    del pr, x
+                out.append(rec)
+                torch.cuda.empty_cache()
+    return out
+
+
 def kernel_rates(torch, pmg, perfmodel, np, pr, dim, n, p, reps):
     """Per-call rates on the finest level (HIP events on the launch stream) and the roofline
     numbers of the smoother color launch and of the apply."""
@@ -344,6 +425,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="leave out the degree sweep and the 128^3 rates")
     ap.add_argument("--extras", action="store_true", help="also the 48^3 Q6 perturbed-mesh problem")
     ap.add_argument("--counters", action="store_true", help="short kernel runs for rocprofv3 counter passes")
+    ap.add_argument("--table1", action="store_true", help="only the Table 1 iteration-count grid (minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -359,6 +441,9 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         return counters_mode(torch, pmg, np)
+    if args.table1:
+        print(json.dumps({"table1_fcg_iterations": bench_table1(torch, pmg)}), flush=True)
+        return 0
     dim, n, p, seed = HEADLINE
     dev = "cuda:0"
     log(f"bench: setup 3D n={n} Q{p}")
@@ -474,6 +559,7 @@ def main():
         out["n128_q4"] = r128
         del pr128
         torch.cuda.empty_cache()
+        out["local_solvers_32"] = bench_local_solvers(torch, pmg, perfmodel, np, max(3, reps // 2))
     if not args.no_batch:
         log("bench: 16-problem batch (FP32-MG in FP64 CG) and the same solves one by one")
         out["batched"] = bench_batch(max(1, min(args.steps, 3)), torch, pmg, rhs_vector)
