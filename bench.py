@@ -2,7 +2,9 @@
 """Benchmark of the local p-multigrid patch-smoother solver on one MI355X.
 
 Headline workload: 3D Poisson on the unit cube, 64^3 hexahedra, Q4 Gauss-Lobatto elements
-(16,974,593 nodes), homogeneous Dirichlet, seeded uniform[-1,1] right-hand side; h-multigrid
+(16,974,593 nodes), homogeneous Dirichlet, right-hand side b = M f of a seeded uniform[-1,1]
+nodal source f (M the consistent mass matrix, applied on the GPU before the timing; --rhs
+nodal takes b = f instead); h-multigrid
 V(1,1) (levels 2..64 cells) with the vertex-patch smoother whose local solver is one half
 V-cycle over the p-levels 4 -> 3 -> 1, inside flexible CG, all FP64.  This is the largest
 single-GPU configuration of the task's list (64^3, degrees 2..8) at the degree of its
@@ -25,7 +27,7 @@ whole path).  value = nodes x V-cycles / time (DoF/s per V-cycle).  Beside it:
   * the CPU oracle on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batch] [--no-sweep]
-                    [--extras]        (also the 48^3 Q6 perturbed mesh with a coefficient)
+                    [--rhs mass|nodal] [--extras]   (also the 48^3 Q6 perturbed mesh with a coefficient)
     python bench.py --counters       (short kernel runs for rocprofv3 counter passes)
     python bench.py --table1         (outer iteration counts on the grid of Table 1)
 """
@@ -227,7 +229,19 @@ def _solve_times(torch, pmg, pr, b, precs, steps, warmup=1):
     return out
 
 
-def bench_degree_sweep(torch, pmg, rhs_vector, steps, degrees):
+def make_rhs(torch, pmg, pr, f, mode):
+    """The right-hand side on the device: b = M f (mass matrix of the finest level, on the
+    GPU) or b = f (nodal mode).  f is zero on the Dirichlet boundary, and so is b."""
+    fd = torch.as_tensor(f, dtype=torch.float64, device="cuda:0")
+    if mode == "nodal":
+        return fd
+    b = torch.empty_like(fd)
+    pmg.mass_operator(pr, pr.finest, fd, b)
+    torch.cuda.synchronize()
+    return b
+
+
+def bench_degree_sweep(torch, pmg, rhs_vector, steps, degrees, rhs="mass"):
     """3D Poisson, 64^3 hexes, p = 2..8 (paper p-hierarchies), seeds 300 + p: FP64 and FP32
     multigrid inside the FP64 flexible CG.  (Cartesian meshes store no operator data, so a
     bfloat16-storage arm would equal FP32 and is not run.)"""
@@ -235,7 +249,7 @@ def bench_degree_sweep(torch, pmg, rhs_vector, steps, degrees):
     for p in degrees:
         log(f"bench: degree sweep 64^3 Q{p}")
         pr = pmg.make_problem(3, 64, p)
-        b = torch.as_tensor(rhs_vector(3, 64, p, 300 + p), dtype=torch.float64, device="cuda:0")
+        b = make_rhs(torch, pmg, pr, rhs_vector(3, 64, p, 300 + p), rhs)
         rec = {"degree": p, "n_dofs": pr.n_nodes[-1]}
         rec.update(_solve_times(torch, pmg, pr, b, ((pmg.FP64, "fp64_mg"), (pmg.FP32, "fp32_mg")), steps))
         rec["fp32_mg_speedup"] = rec["fp64_mg"]["time_to_solution_s"] / rec["fp32_mg"]["time_to_solution_s"]
@@ -426,6 +440,8 @@ def main():
     ap.add_argument("--extras", action="store_true", help="also the 48^3 Q6 perturbed-mesh problem")
     ap.add_argument("--counters", action="store_true", help="short kernel runs for rocprofv3 counter passes")
     ap.add_argument("--table1", action="store_true", help="only the Table 1 iteration-count grid (minutes)")
+    ap.add_argument("--rhs", choices=("mass", "nodal"), default="mass",
+                    help="b = M f (default) or b = f, f seeded uniform[-1,1] nodal values, zero on the boundary")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -451,7 +467,7 @@ def main():
     pr = pmg.make_problem(dim, n, p)
     t_setup = time.perf_counter() - t0
     N = pr.n_nodes[-1]
-    b = torch.as_tensor(rhs_vector(dim, n, p, seed), dtype=torch.float64, device=dev)
+    b = make_rhs(torch, pmg, pr, rhs_vector(dim, n, p, seed), args.rhs)
     x = torch.empty_like(b)
 
     def run_solves(prec, k):
@@ -510,7 +526,7 @@ def main():
     roof_apply = {"bound": "hbm", "achieved": round(ap_["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(ap_["achieved_gbs"] / HBM_PEAK_GBS, 4),
                   "traffic": measured_traffic("k_apply_fp64_q4_64cube"),
-                  "kernel": f"k_apply<3,double,4> (finest level {n}^3, v = A u, one launch)",
+                  "kernel": f"k_march<double,4> (finest level {n}^3, v = A u, one launch)",
                   "avg_launch_us": round(ap_["avg_launch_us"], 2), "bytes_per_launch": ap_["bytes_per_launch"],
                   "fp32_avg_launch_us": round(ap_["fp32_avg_launch_us"], 2),
                   "fp32_frac_hbm": round(ap_["fp32_achieved_gbs"] / HBM_PEAK_GBS, 4)}
@@ -527,7 +543,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded uniform[-1,1] right-hand side)",
+        "data": ("synthetic: b = M f, f seeded uniform[-1,1] nodal values (zero on the boundary)"
+                 if args.rhs == "mass" else "synthetic: b = f, seeded uniform[-1,1] nodal values"),
         "config": {"workload": f"3D Poisson, unit cube, {n}^3 hexes, Q{p} GLL, Dirichlet, FP64 h-MG(V(1,1), "
                                f"vertex-patch smoother, local half V-cycle p=4->3->1) in flexible CG to rtol 1e-8",
                    "n_dofs": N, "n_cells": n ** dim, "degree": p, "parallelism": "single GPU"},
@@ -546,7 +563,7 @@ def main():
     del pr, b, x, z
     torch.cuda.empty_cache()
     if not args.no_sweep:
-        out["degree_sweep_64"] = bench_degree_sweep(torch, pmg, rhs_vector, 1, [2, 3, 5, 6, 7, 8])
+        out["degree_sweep_64"] = bench_degree_sweep(torch, pmg, rhs_vector, 1, [2, 3, 5, 6, 7, 8], args.rhs)
         log("bench: 128^3 Q4 rates (working set beyond the last-level cache)")
         pr128 = pmg.make_problem(3, 128, 4)
         r128, sm128, ap128 = kernel_rates(torch, pmg, perfmodel, np, pr128, 3, 128, 4, max(3, reps // 4))

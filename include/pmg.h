@@ -180,6 +180,15 @@ int pmg_device_init(pmg_problem *pr);
  * degree-p operator; boundary rows copy u.  u and v must not overlap. */
 int pmg_apply_operator(pmg_problem *pr, int hlevel, int prec, const void *u, void *v, void *stream);
 
+/* v = M_l u on h-level `hlevel`: the consistent mass matrix of the degree-p elements (the
+ * Gram matrix of the nodal basis, Sec. 2, with the exact (p+1)-point Gauss rule per
+ * direction) on the Cartesian mesh, matrix-free and sum-factorized like the operator apply;
+ * rows and columns of the Dirichlet boundary nodes are zero.  Used to form the right-hand
+ * side b = M f of a nodal source f.  u and v: device vectors of the level's
+ * (p n + 1)^dim nodes in the precision `prec`, must not overlap; launched on `stream`.
+ * Returns PMG_ERR_UNSUPPORTED on the general (mapped-mesh) path. */
+int pmg_mass_operator(pmg_problem *pr, int hlevel, int prec, const void *u, void *v, void *stream);
+
 /* r = b - A_l u on h-level `hlevel` (boundary rows: b_i - u_i).  r must not overlap u, b. */
 int pmg_residual(pmg_problem *pr, int hlevel, int prec, const void *b, const void *u, void *r,
                  void *stream);

@@ -467,14 +467,18 @@ struct ApplyArgs {
   T c;
   int n;       // cells per direction
   int ntile;   // tiles per direction
-  int n_tiles; // total tiles
+  int n_tiles; // total tiles (workgroups)
+  int mt, mty, zc;  // marching apply: tiles in x and in y, cell layers per z segment
   const T *u;
   const T *b;  // residual mode
   T *out;
 };
 
-template <int DIM, typename T, int NT, int P, int TC, bool RESID>
+// MASS: v = c (M (x) M (x) M) u instead, the consistent mass matrix (c = h^d), with zero rows
+// and columns on the Dirichlet boundary.
+template <int DIM, typename T, int NT, int P, int TC, bool RESID, bool MASS = false>
 struct ApplyBody {
+  static_assert(!(RESID && MASS), "the mass apply has no residual form");
   static constexpr int NI = P * (TC + 1) + 1, NO = P * TC;
   static constexpr int NId = ipow(NI, DIM), NOd = ipow(NO, DIM);
   using RS = LapScratch<DIM, NI, NO>;
@@ -543,13 +547,17 @@ struct ApplyBody {
         },
         [&](int e, T x) { in[e] = x; });
     PMG_SYNC();
-    laplace_sf<DIM, PatTile<P, TC>, NT>(tid, in, outl, (const T *)nullptr, a.c, a.Kt, a.Mt, ab, in);
+    if constexpr (MASS)
+      kron_all<DIM, PatTile<P, TC>, NT, false>(tid, in, outl, a.Mt, ab, (T *)nullptr);
+    else
+      laplace_sf<DIM, PatTile<P, TC>, NT>(tid, in, outl, (const T *)nullptr, a.c, a.Kt, a.Mt, ab, in);
     PMG_SYNC();
     auto finish = [&](int e, T uv, T bv) {
       bool bnd;
       const int gi = out_index(e, bnd);
       const int ox = e % bx, oy = (e / bx) % by, oz = DIM == 3 ? e / (bx * by) : 0;
       T val = bnd ? uv : outl[ox + NO * (oy + NO * oz)];
+      if (MASS) val = bnd ? T(0) : a.c * val;
       if (RESID) val = bv - val;
       a.out[gi] = val;
     };
@@ -657,9 +665,15 @@ struct ApplyBody {
     // G = Ky A + My B in the dead input tile; out = c (Kz C + Mz G))
     using Pat = PatTile<P, TC>;
     constexpr int SA = NO * NI * NI, SC = NO * NO * NI;
-    contract2<0, NI, NI, NI, Pat, NT>(tid, in, ab, a.Mt, ab + SA, a.Kt);
-    PMG_SYNC();
-    contract_pair<1, NO, NI, NI, Pat, NT>(tid, ab, ab + SA, in, in + SC, a.Mt, a.Kt);
+    if constexpr (MASS) {  // A = Mx u; C = My A
+      contract1<0, NI, NI, NI, Pat, NT, false>(tid, in, ab, a.Mt);
+      PMG_SYNC();
+      contract1<1, NO, NI, NI, Pat, NT, false>(tid, ab, in, a.Mt);
+    } else {
+      contract2<0, NI, NI, NI, Pat, NT>(tid, in, ab, a.Mt, ab + SA, a.Kt);
+      PMG_SYNC();
+      contract_pair<1, NO, NI, NI, Pat, NT>(tid, ab, ab + SA, in, in + SC, a.Mt, a.Kt);
+    }
     PMG_SYNC();
     // b, and u where an owned node is on the mesh boundary (only tiles at the mesh faces have
     // such nodes), are read here so that their loads overlap the last stage, where the
@@ -678,7 +692,10 @@ struct ApplyBody {
 #pragma unroll
         for (int z = 0; z < ZS; ++z) ub[q][z] = u[gcol[q] + m2 * (P * c0[2] + zidx(z))];
     }
-    contract_final<2, NO, NO, NI, Pat, NT>(tid, in, in + SC, outl, (const T *)nullptr, a.c, a.Kt, a.Mt);
+    if constexpr (MASS)
+      contract1<2, NO, NO, NI, Pat, NT, false>(tid, in, outl, a.Mt);  // Mz C
+    else
+      contract_final<2, NO, NO, NI, Pat, NT>(tid, in, in + SC, outl, (const T *)nullptr, a.c, a.Kt, a.Mt);
     PMG_SYNC();
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
@@ -690,7 +707,11 @@ struct ApplyBody {
         const int gz = P * c0[2] + oz;
         const bool bnd = bxyc[q] || gz == 0 || gz == m - 1;
         T val = outl[lcol[q] + NO * NO * oz];
-        if (edge && bnd) val = ub[q][z];
+        if constexpr (MASS) {
+          val = (edge && bnd) ? T(0) : a.c * val;
+        } else {
+          if (edge && bnd) val = ub[q][z];
+        }
         if constexpr (RESID) val = bb[q][z] - val;
         a.out[gcol[q] + m2 * gz] = val;
       }
@@ -699,6 +720,9 @@ struct ApplyBody {
 };
 
 }  // namespace pmg
+
+// the operator apply that marches in z
+#include "march.h"
 
 // h-transfers and the coarse solve
 #include "transfer.h"

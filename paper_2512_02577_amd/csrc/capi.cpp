@@ -237,20 +237,25 @@ int general_local(pmg_problem *pr, int hl, int first, int nb, const T *r, T *d, 
 }
 
 template <typename T>
-int do_apply(pmg_problem *pr, int l, bool resid, const T *b, const T *u, T *out, hipStream_t s, int store = ST_NATIVE) {
-  if (pr->general) return general_apply<T>(pr, l, resid, b, u, out, s, store);
+int do_apply(pmg_problem *pr, int l, bool resid, const T *b, const T *u, T *out, hipStream_t s, int store = ST_NATIVE,
+             bool mass = false) {
+  if (pr->general) {
+    if (mass) return fail(PMG_ERR_UNSUPPORTED, "the mass matrix is applied on the Cartesian mesh only");
+    return general_apply<T>(pr, l, resid, b, u, out, s, store);
+  }
   const int tc = tile_cells(pr->p);
   ApplyArgs<T> a{};
   a.Kt = pr->pd<T>().tabs.Kt;
   a.Mt = pr->pd<T>().tabs.Mt;
-  a.c = (T)pr->cscale(l);
+  // Laplacian: h^(d-2) sum_k K_k (x) M_others of the unit-interval matrices; mass: h^d
+  a.c = mass ? (T)std::pow(1.0 / pr->sizes[l], pr->dim) : (T)pr->cscale(l);
   a.n = pr->sizes[l];
   a.ntile = (a.n + tc - 1) / tc;
   a.n_tiles = pr->dim == 3 ? a.ntile * a.ntile * a.ntile : a.ntile * a.ntile;
   a.u = u;
   a.b = b;
   a.out = out;
-  PMG_TRY(launch_apply<T>(pr->dim, pr->p, resid, a, pr->arena, s));
+  PMG_TRY(launch_apply<T>(pr->dim, pr->p, mass ? 2 : (resid ? 1 : 0), a, pr->arena, s));
   return PMG_OK;
 }
 
@@ -966,6 +971,17 @@ int pmg_apply_operator(pmg_problem *pr, int hlevel, int prec, const void *u, voi
   hipStream_t s = (hipStream_t)stream;
   if (prec == PMG_FP64) return do_apply<double>(pr, hlevel, false, nullptr, (const double *)u, (double *)v, s);
   return do_apply<float>(pr, hlevel, false, nullptr, (const float *)u, (float *)v, s, store_of(prec));
+}
+
+int pmg_mass_operator(pmg_problem *pr, int hlevel, int prec, const void *u, void *v, void *stream) {
+  if (int rc = check_ready(pr)) return rc;
+  if (int rc = check_level(pr, hlevel)) return rc;
+  if (int rc = check_prec(prec)) return rc;
+  if (!u || !v) return fail(PMG_ERR_INVALID_ARG, "u or v is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == PMG_FP64)
+    return do_apply<double>(pr, hlevel, false, nullptr, (const double *)u, (double *)v, s, ST_NATIVE, true);
+  return do_apply<float>(pr, hlevel, false, nullptr, (const float *)u, (float *)v, s, store_of(prec), true);
 }
 
 int pmg_residual(pmg_problem *pr, int hlevel, int prec, const void *b, const void *u, void *r, void *stream) {

@@ -187,23 +187,39 @@ struct EmuSmooth {
   };
 };
 
-template <int DIM, bool RESID>
+// kind: 0 v = A u, 1 v = b - A u, 2 v = M u (mass).  3D degrees with a marching apply run
+// that body (as the library does); zsplit 0 takes the library's z segments, 1 one segment
+// per xy tile (every layer of the mesh in one workgroup).
+template <int DIM, int KIND>
 struct EmuApply {
+  static constexpr bool RESID = KIND == 1, MASS = KIND == 2;
   template <int P>
   struct F {
     template <int NT>
-    static int go(ApplyArgs<double> a) {
-      constexpr int TC = tile_cells(P);
-      using B = ApplyBody<DIM, double, NT, P, TC, RESID>;
-      std::vector<double> lds(B::size);
-      a.ntile = (a.n + TC - 1) / TC;
-      a.n_tiles = DIM == 3 ? a.ntile * a.ntile * a.ntile : a.ntile * a.ntile;
-      launch<NT>(a.n_tiles, lds, [&](int tid, int blk, double *ar) { B::run(tid, blk, ar, a); });
-      return 0;
+    static int go(ApplyArgs<double> a, int zsplit) {
+      if constexpr (DIM == 3 && march_tile(P) > 0) {
+        using B = MarchBody<double, NT, P, march_tile(P), march_tile_y(P), march_group(P), P * (tile_cells(P) + 1) + 1,
+                            RESID, MASS>;
+        std::vector<double> lds(B::size);
+        int nseg;
+        march_geometry(a.n, march_tile(P), march_tile_y(P), zsplit ? 1 : kMarchBlocks, a.mt, a.mty, nseg, a.zc);
+        a.n_tiles = a.mt * a.mty * nseg;
+        launch<NT>(a.n_tiles, lds, [&](int tid, int blk, double *ar) { B::run(tid, blk, ar, a); });
+        return 0;
+      } else {
+        constexpr int TC = tile_cells(P);
+        using B = ApplyBody<DIM, double, NT, P, TC, RESID, MASS>;
+        std::vector<double> lds(B::size);
+        a.ntile = (a.n + TC - 1) / TC;
+        a.n_tiles = DIM == 3 ? a.ntile * a.ntile * a.ntile : a.ntile * a.ntile;
+        launch<NT>(a.n_tiles, lds, [&](int tid, int blk, double *ar) { B::run(tid, blk, ar, a); });
+        return 0;
+      }
     }
-    static int run(const ApplyArgs<double> &a, int lanes) {
-      if (lanes == 0) return go<1>(a);
-      if (lanes == 1) return go<apply_threads(P)>(a);
+    static int run(const ApplyArgs<double> &a, int lanes, int zsplit) {
+      if (lanes == 0) return go<1>(a, zsplit);
+      constexpr int NT = (DIM == 3 && march_tile(P) > 0) ? march_threads(P) : apply_threads(P);
+      if (lanes == 1) return go<NT>(a, zsplit);
       return -1;
     }
   };
@@ -447,20 +463,27 @@ int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const doubl
   return dispatch_hierarchy<EmuSmooth<2>::F>(p, code, a, n, 1, true, n_blocks, lanes, 0);
 }
 
-int pmgemu_apply(int dim, int n, int p, int resid, const double *u, const double *b, double *out, int lanes) {
+int pmgemu_apply(int dim, int n, int p, int kind, const double *u, const double *b, double *out, int lanes,
+                 int zsplit) {
   Tables t;
   build_tables(dim, p, std::vector<int>{p}, {}, n, t);
   ApplyArgs<double> a{};
   a.Kt = t.Kt.data();
   a.Mt = t.Mt.data();
-  a.c = cscale(dim, n);
+  a.c = kind == 2 ? 1.0 / ((dim == 3 ? (double)n : 1.0) * n * n) : cscale(dim, n);
   a.n = n;
   a.u = u;
   a.b = b;
   a.out = out;
-  if (dim == 3)
-    return resid ? dispatch_degree<EmuApply<3, true>::F>(p, a, lanes) : dispatch_degree<EmuApply<3, false>::F>(p, a, lanes);
-  return resid ? dispatch_degree<EmuApply<2, true>::F>(p, a, lanes) : dispatch_degree<EmuApply<2, false>::F>(p, a, lanes);
+  switch (kind + 3 * (dim == 3)) {
+    case 0: return dispatch_degree<EmuApply<2, 0>::F>(p, a, lanes, zsplit);
+    case 1: return dispatch_degree<EmuApply<2, 1>::F>(p, a, lanes, zsplit);
+    case 2: return dispatch_degree<EmuApply<2, 2>::F>(p, a, lanes, zsplit);
+    case 3: return dispatch_degree<EmuApply<3, 0>::F>(p, a, lanes, zsplit);
+    case 4: return dispatch_degree<EmuApply<3, 1>::F>(p, a, lanes, zsplit);
+    case 5: return dispatch_degree<EmuApply<3, 2>::F>(p, a, lanes, zsplit);
+    default: return -1;
+  }
 }
 
 int pmgemu_transfer(int dim, int nc, int p, int restrict_, const double *in, double *out) {

@@ -18,7 +18,8 @@ int pmgemu_smooth(int dim, int n, int p, const int *deg, int L, const double *om
                   int n_iter, int color_dir, double *u, const double *b, int lanes, int one, int tabmode);
 int pmgemu_local_solve(int dim, int n, int p, const int *deg, int L, const double *omega, int local, int reinf,
                        int n_iter, int n_blocks, const double *r, double *d, int lanes, int tabmode);
-int pmgemu_apply(int dim, int n, int p, int resid, const double *u, const double *b, double *out, int lanes);
+int pmgemu_apply(int dim, int n, int p, int kind, const double *u, const double *b, double *out, int lanes,
+                 int zsplit);
 int pmgemu_transfer(int dim, int nc, int p, int restrict_, const double *in, double *out);
 int pmgemu_coarse_solve(int dim, int n0, int p, const double *r, double *z, int lanes);
 int pmgemu_metric_apply(int dim, int n, int p, const double *verts, const double *coef, int resid, const double *u,
@@ -47,6 +48,24 @@ int main(int argc, char **argv) {
       ++fails;
     }
   };
+  if (argc > 1 && std::strcmp(argv[1], "apply") == 0) {  // the operator applies only, more mesh sizes
+    for (int dim = 2; dim <= 3; ++dim)
+      for (int p = 1; p <= 8; ++p)
+        for (int n : {1, 2, 3, 4, 5, 9, 17}) {
+          const long N = ipow((long)p * n + 1, dim);
+          if (N > 400000) continue;
+          auto u = rnd(N, 1), b = rnd(N, 2), out = std::vector<double>(N);
+          for (int lanes = 0; lanes <= 1; ++lanes)
+            for (int kind = 0; kind < 3; ++kind)
+              for (int zs = 0; zs < 2; ++zs)
+                check(pmgemu_apply(dim, n, p, kind, u.data(), b.data(), out.data(), lanes, zs), "apply", dim, p, n,
+                      lanes);
+          std::printf("apply dim %d p %d n %d done\n", dim, p, n);
+          std::fflush(stdout);
+        }
+    std::printf("failures: %d\n", fails);
+    return fails != 0;
+  }
   for (int dim = 2; dim <= 3; ++dim)
     for (int p = 1; p <= 8; ++p)
       for (int code = 0; code < 2; ++code) {
@@ -95,8 +114,10 @@ int main(int argc, char **argv) {
                       "local", dim, p, n, lanes);
           if (code == 0) {
             for (int lanes = 0; lanes <= 1; ++lanes) {
-              check(pmgemu_apply(dim, n, p, 1, u.data(), b.data(), out.data(), lanes), "apply", dim, p, n, lanes);
-              check(pmgemu_apply(dim, n, p, 0, u.data(), b.data(), out.data(), lanes), "apply", dim, p, n, lanes);
+              for (int kind = 0; kind < 3; ++kind)
+                for (int zs = 0; zs < 2; ++zs)
+                  check(pmgemu_apply(dim, n, p, kind, u.data(), b.data(), out.data(), lanes, zs), "apply", dim, p,
+                        n, lanes);
             }
             const long Nc = ipow((long)p * n + 1, dim), Nf = ipow(2L * p * n + 1, dim);
             auto fine = rnd(Nf, 4), coarse = std::vector<double>(Nc);

@@ -36,8 +36,8 @@ int launch_local_only(int dim, int p, int hcode, const SmoothArgs<T> &a, int n_b
 }
 
 template <typename T>
-int launch_apply(int dim, int p, bool resid, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s) {
-  return dim == 3 ? Launchers<3, T>::apply(p, resid, a, ar, s) : Launchers<2, T>::apply(p, resid, a, ar, s);
+int launch_apply(int dim, int p, int kind, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s) {
+  return dim == 3 ? Launchers<3, T>::apply(p, kind, a, ar, s) : Launchers<2, T>::apply(p, kind, a, ar, s);
 }
 
 template <typename T>
@@ -58,7 +58,7 @@ int launch_coarse(int dim, const CoarseArgs<T> &a, hipStream_t s) {
 #define PMG_INSTANTIATE(T)                                                                              \
   template int launch_smooth_color<T>(int, int, int, const SmoothArgs<T> &, const Arena &, hipStream_t); \
   template int launch_local_only<T>(int, int, int, const SmoothArgs<T> &, int, const Arena &, hipStream_t); \
-  template int launch_apply<T>(int, int, bool, const ApplyArgs<T> &, const Arena &, hipStream_t);       \
+  template int launch_apply<T>(int, int, int, const ApplyArgs<T> &, const Arena &, hipStream_t);       \
   template int launch_restrict<T>(int, int, const TransferArgs<T> &, hipStream_t);                       \
   template int launch_prolong_add<T>(int, int, const TransferArgs<T> &, hipStream_t);                    \
   template int launch_coarse<T>(int, const CoarseArgs<T> &, hipStream_t);

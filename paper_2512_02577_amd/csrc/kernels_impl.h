@@ -65,20 +65,31 @@ __global__ __launch_bounds__(patch_threads(P)) void k_local_g(SmoothArgs<T> a, i
 }
 
 // ---- operator apply: one workgroup per tile ----
-template <int DIM, typename T, int P, bool RESID>
+template <int DIM, typename T, int P, bool RESID, bool MASS>
 __global__ __launch_bounds__(apply_threads(P)) void k_apply(ApplyArgs<T> a) {
-  using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID>;
+  using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID, MASS>;
   B::run(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
-template <int DIM, typename T, int P, bool RESID>
+template <int DIM, typename T, int P, bool RESID, bool MASS>
 __global__ __launch_bounds__(apply_threads(P)) void k_apply_g(ApplyArgs<T> a, void *garena) {
-  using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID>;
+  using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID, MASS>;
   T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
   for (int blk = blockIdx.x; blk < a.n_tiles; blk += gridDim.x) {
     B::run(threadIdx.x, blk, ar, a);
     __syncthreads();
   }
+}
+
+// ---- operator apply marching in z: one workgroup per xy tile and z segment (3D) ----
+template <typename T, int P, bool RESID = false, bool MASS = false>
+using March = MarchBody<T, march_threads(P), P, march_tile(P), march_tile_y(P), march_group(P),
+                        P * (tile_cells(P) + 1) + 1, RESID, MASS>;
+
+template <typename T, int P, bool RESID, bool MASS>
+__global__ __launch_bounds__(march_threads(P)) void k_march(ApplyArgs<T> a) {
+  using B = March<T, P, RESID, MASS>;
+  B::run(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
 // ---- h-transfer: one 1D pass, one thread per output entry ----
@@ -176,20 +187,44 @@ struct ApplySizeL {
   template <int P>
   struct F {
     static int run(size_t *out) {
-      *out = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), false>::size * sizeof(T);
+      if constexpr (DIM == 3 && march_tile(P) > 0)
+        *out = March<T, P>::size * sizeof(T);
+      else
+        *out = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), false>::size * sizeof(T);
       return 0;
     }
   };
 };
 
-template <typename T, int DIM, bool RESID>
+// KIND: 0 v = A u, 1 v = b - A u, 2 v = c M u (the mass matrix)
+template <typename T, int DIM, int KIND>
 struct ApplyL {
+  static constexpr bool RESID = KIND == 1, MASS = KIND == 2;
   template <int P>
   struct F {
     static int run(const ApplyArgs<T> &a, const Arena &ar, hipStream_t s) {
-      using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID>;
-      return launch_arena(k_apply<DIM, T, P, RESID>, k_apply_g<DIM, T, P, RESID>, a.n_tiles, apply_threads(P),
-                          B::size * sizeof(T), ar, s, a);
+      if constexpr (DIM == 3 && march_tile(P) > 0) if (march_fits<T>(P, (long)P * a.n + 1)) {
+        constexpr size_t bytes = March<T, P>::size * sizeof(T);
+        if (bytes > ar.lds_max) return -3;
+        if (bytes > 65536) {  // raise the kernel's limit once, to the device maximum
+          static thread_local bool raised = false;
+          if (!raised) {
+            if (hipFuncSetAttribute((const void *)k_march<T, P, RESID, MASS>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)ar.lds_max) != hipSuccess)
+              return -4;
+            raised = true;
+          }
+        }
+        ApplyArgs<T> b = a;
+        int nseg;
+        march_geometry(a.n, march_tile(P), march_tile_y(P), kMarchBlocks, b.mt, b.mty, nseg, b.zc);
+        b.n_tiles = b.mt * b.mty * nseg;
+        hipLaunchKernelGGL((k_march<T, P, RESID, MASS>), dim3(b.n_tiles), dim3(march_threads(P)), bytes, s, b);
+        return hipGetLastError() == hipSuccess ? 0 : -4;
+      }
+      using B = ApplyBody<DIM, T, apply_threads(P), P, tile_cells(P), RESID, MASS>;
+      return launch_arena(k_apply<DIM, T, P, RESID, MASS>, k_apply_g<DIM, T, P, RESID, MASS>, a.n_tiles,
+                          apply_threads(P), B::size * sizeof(T), ar, s, a);
     }
   };
 };
@@ -238,9 +273,13 @@ int Launchers<DIM, T>::local(int p, int hcode, const SmoothArgs<T> &a, int nb, c
   return dispatch_hierarchy<detail::LocalL<T>::template D<DIM>::template F>(p, hcode, a, nb, ar, s);
 }
 template <int DIM, typename T>
-int Launchers<DIM, T>::apply(int p, bool resid, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s) {
-  return resid ? dispatch_degree<detail::ApplyL<T, DIM, true>::template F>(p, a, ar, s)
-               : dispatch_degree<detail::ApplyL<T, DIM, false>::template F>(p, a, ar, s);
+int Launchers<DIM, T>::apply(int p, int kind, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s) {
+  switch (kind) {
+    case 0: return dispatch_degree<detail::ApplyL<T, DIM, 0>::template F>(p, a, ar, s);
+    case 1: return dispatch_degree<detail::ApplyL<T, DIM, 1>::template F>(p, a, ar, s);
+    case 2: return dispatch_degree<detail::ApplyL<T, DIM, 2>::template F>(p, a, ar, s);
+    default: return -1;
+  }
 }
 template <int DIM, typename T>
 int Launchers<DIM, T>::restrict_(int p, const TransferArgs<T> &a, hipStream_t s) {

@@ -42,7 +42,8 @@ struct Launchers {
   static size_t apply_bytes(int p);
   static int smooth(int p, int hcode, const SmoothArgs<T> &a, const Arena &ar, hipStream_t s);
   static int local(int p, int hcode, const SmoothArgs<T> &a, int nb, const Arena &ar, hipStream_t s);
-  static int apply(int p, bool resid, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s);
+  // kind: 0 v = A u, 1 v = b - A u, 2 v = c M u
+  static int apply(int p, int kind, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s);
   static int restrict_(int p, const TransferArgs<T> &a, hipStream_t s);
   static int prolong(int p, const TransferArgs<T> &a, hipStream_t s);
   static int coarse(const CoarseArgs<T> &a, hipStream_t s);
@@ -87,7 +88,7 @@ template <typename T>
 int launch_local_only(int dim, int p, int hcode, const SmoothArgs<T> &a, int n_blocks, const Arena &ar,
                       hipStream_t s);
 template <typename T>
-int launch_apply(int dim, int p, bool resid, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s);
+int launch_apply(int dim, int p, int kind, const ApplyArgs<T> &a, const Arena &ar, hipStream_t s);
 template <typename T>
 int launch_restrict(int dim, int p, const TransferArgs<T> &a, hipStream_t s);
 template <typename T>

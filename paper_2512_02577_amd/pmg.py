@@ -70,6 +70,7 @@ def lib() -> ctypes.CDLL:
             "pmg_set_coefficient": (_ip, [_vp, _ip, _ip, P(_dp)]),
             "pmg_device_init": (_ip, [_vp]),
             "pmg_apply_operator": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp]),
+            "pmg_mass_operator": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp]),
             "pmg_residual": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp, _vp]),
             "pmg_smooth": (_ip, [_vp, _ip, _ip, _ip, _vp, _vp, _vp]),
             "pmg_local_solve": (_ip, [_vp, _ip, _ip, _ip, _ip, _vp, _vp, _vp]),
@@ -261,6 +262,12 @@ def apply_operator(pr: Problem, hlevel: int, u, v, bf16: bool = False) -> None:
     n = _nodes(pr, hlevel)
     _check(lib().pmg_apply_operator(pr.handle, hlevel, _prec_of(u, bf16), _ptr(u, n), _ptr(v, n, u.dtype),
                                     _stream()))
+
+
+def mass_operator(pr: Problem, hlevel: int, u, v) -> None:
+    """v = M u (consistent mass matrix, zero Dirichlet rows and columns; Cartesian mesh)."""
+    n = _nodes(pr, hlevel)
+    _check(lib().pmg_mass_operator(pr.handle, hlevel, _prec_of(u), _ptr(u, n), _ptr(v, n, u.dtype), _stream()))
 
 
 def residual(pr: Problem, hlevel: int, b, u, r) -> None:

@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_2512_02577_amd/csrc/bodies.h", "paper_2512_02577_amd/csrc/sumfac.h",
                   "paper_2512_02577_amd/csrc/kernels_impl.h", "paper_2512_02577_amd/csrc/dispatch.h",
                   "paper_2512_02577_amd/csrc/constants.h", "paper_2512_02577_amd/csrc/launch.h",
+                  "paper_2512_02577_amd/csrc/march.h",
                   "paper_2512_02577_amd/csrc/kernels_3d_f64.hip"]
 COPY_KERNEL = re.compile(r"copyBuffer|copy_kernel|CopyKernel", re.I)
 

@@ -14,8 +14,10 @@ import os
 import numpy as np
 import pytest
 
-from oracle.assembly import stiffness_matrix
-from oracle.mesh import StructuredMesh, p_hierarchy
+import scipy.sparse as sp
+
+from oracle.assembly import mass_matrix, stiffness_matrix
+from oracle.mesh import StructuredMesh, boundary_nodes, p_hierarchy
 from oracle.smoother import LevelSmoother
 from oracle.solver import MultigridProblem
 from oracle.transfer import h_prolongation
@@ -47,19 +49,30 @@ def cd(a):
 
 @pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("dim,n,p", [(2, 4, 1), (2, 5, 2), (2, 5, 3), (2, 3, 7), (2, 3, 8), (3, 3, 1), (3, 5, 2),
-                                     (3, 4, 3), (3, 3, 4), (3, 3, 5), (3, 2, 6), (3, 2, 7), (3, 2, 8)])
-def test_apply_and_residual(emu, dim, n, p, lanes):
-    A = stiffness_matrix(StructuredMesh(dim, n), p)
+                                     (3, 4, 3), (3, 3, 4), (3, 5, 4), (3, 6, 4), (3, 3, 5), (3, 4, 5), (3, 2, 6), (3, 2, 7),
+                                     (3, 2, 8), (3, 17, 1), (3, 9, 2)])
+def test_apply_residual_and_mass(emu, dim, n, p, lanes):
+    # the 3D degrees 1-5 run the marching apply; n = 17 (p = 1) and 9 (p = 2) leave a partial
+    # xy tile, n = 5 (p = 4) one at the upper end with the extra boundary row; zsplit 1 walks
+    # every layer in one workgroup, 0 takes the library's z segments
+    mesh = StructuredMesh(dim, n)
+    A = stiffness_matrix(mesh, p)
+    bnd = boundary_nodes(dim, n, p)
+    keep = sp.diags((~bnd).astype(np.float64))
+    Mm = (keep @ mass_matrix(mesh, p) @ keep).tocsr()
     u = np.random.default_rng(1).uniform(-1, 1, A.shape[0])
     b = rhs_vector(dim, n, p, 2)
-    v = np.zeros_like(u)
-    r = np.zeros_like(u)
-    assert emu.pmgemu_apply(dim, n, p, 0, P(u), P(b), P(v), lanes) == 0
-    assert emu.pmgemu_apply(dim, n, p, 1, P(u), P(b), P(r), lanes) == 0
     ref = A @ u
     s = abs(ref).max()
-    assert abs(v - ref).max() <= 1e-13 * s
-    assert abs(r - (b - ref)).max() <= 1e-13 * s
+    for zsplit in (0, 1):
+        v, r, w = np.zeros_like(u), np.zeros_like(u), np.zeros_like(u)
+        assert emu.pmgemu_apply(dim, n, p, 0, P(u), P(b), P(v), lanes, zsplit) == 0
+        assert emu.pmgemu_apply(dim, n, p, 1, P(u), P(b), P(r), lanes, zsplit) == 0
+        assert emu.pmgemu_apply(dim, n, p, 2, P(u), P(b), P(w), lanes, zsplit) == 0
+        assert abs(v - ref).max() <= 1e-13 * s
+        assert abs(r - (b - ref)).max() <= 1e-13 * s
+        mref = Mm @ u
+        assert abs(w - mref).max() <= 1e-13 * abs(mref).max()
 
 
 CASES = [(2, 4, 2, None, "half"), (2, 5, 3, [1, 2, 3], "half"), (2, 4, 3, None, "full"), (3, 3, 2, None, "half"),
