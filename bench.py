@@ -401,7 +401,8 @@ def counters_mode(torch, pmg, np):
     """Short runs of the kernels whose HBM traffic is recorded under profiles/, for
     `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` passes: a plain device copy of
     1 GiB (the calibration: 1 GiB read and 1 GiB written per dispatch), then at 64^3 and
-    128^3 Q4 two FP64 smoother applications (8 color launches each) and three applies."""
+    128^3 Q4 two FP64 smoother applications (8 color launches each) and three applies, and
+    at 64^3 Q8 three applies."""
     dev = "cuda:0"
     x = torch.empty(2 ** 27, dtype=torch.float64, device=dev).uniform_(-1, 1)
     y = torch.empty_like(x)
@@ -410,14 +411,14 @@ def counters_mode(torch, pmg, np):
     torch.cuda.synchronize()
     del x, y
     torch.cuda.empty_cache()
-    for n in (64, 128):
-        log(f"bench: counter runs at {n}^3 Q4")
-        pr = pmg.make_problem(3, n, 4)
+    for n, p in ((64, 4), (128, 4), (64, 8)):
+        log(f"bench: counter runs at {n}^3 Q{p}")
+        pr = pmg.make_problem(3, n, p)
         N = pr.n_nodes[-1]
         u = torch.as_tensor(np.random.default_rng(3).uniform(-1, 1, N), dtype=torch.float64, device=dev)
         b = torch.as_tensor(np.random.default_rng(4).uniform(-1, 1, N), dtype=torch.float64, device=dev)
         v = torch.empty_like(u)
-        for _ in range(2):
+        for _ in range(2 if p == 4 else 0):
             pmg.smooth(pr, pr.finest, u, b, 1)
         for _ in range(3):
             pmg.apply_operator(pr, pr.finest, u, v)
@@ -525,7 +526,7 @@ def main():
                  "fp32_frac_hbm": round(sm["fp32_achieved_gbs"] / HBM_PEAK_GBS, 4)})
     roof_apply = {"bound": "hbm", "achieved": round(ap_["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(ap_["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                  "traffic": measured_traffic("k_apply_fp64_q4_64cube"),
+                  "traffic": measured_traffic("k_march_fp64_q4_64cube"),
                   "kernel": f"k_march<double,4> (finest level {n}^3, v = A u, one launch)",
                   "avg_launch_us": round(ap_["avg_launch_us"], 2), "bytes_per_launch": ap_["bytes_per_launch"],
                   "fp32_avg_launch_us": round(ap_["fp32_avg_launch_us"], 2),
@@ -572,7 +573,7 @@ def main():
                      "smooth_launch_frac_fp64_valu": sm128["achieved_tflops"] / FP64_PEAK_TFLOPS,
                      "apply_frac_hbm": ap128["achieved_gbs"] / HBM_PEAK_GBS, "apply_us": ap128["avg_launch_us"],
                      "smooth_traffic": measured_traffic("k_smooth_fp64_q4_128cube"),
-                     "apply_traffic": measured_traffic("k_apply_fp64_q4_128cube")})
+                     "apply_traffic": measured_traffic("k_march_fp64_q4_128cube")})
         out["n128_q4"] = r128
         del pr128
         torch.cuda.empty_cache()

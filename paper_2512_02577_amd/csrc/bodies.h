@@ -91,7 +91,7 @@ struct PatchBody {
   static constexpr int off_B = nd + Nd;
   static constexpr int phaseR_end = off_B + (DIM == 3 ? n * N * N : n * N);
   static constexpr int off_d = nd;
-  static constexpr int NRED = 4;  // per-wave partial sums of block_sum (up to 4 waves)
+  static constexpr int NRED = 8;  // per-wave partial sums of block_sum (up to 8 waves)
   static constexpr int off_red = 2 * nd;
   static constexpr int lower_size(int l) { return l <= 0 ? 0 : 2 * ndl(l) + lower_size(l - 1); }  // levels 1..l
   static constexpr int off_lr(int l) { return 2 * nd + NRED + lower_size(l - 1); }

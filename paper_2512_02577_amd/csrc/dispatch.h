@@ -69,8 +69,10 @@ inline int hierarchy_code(int p, const int *deg, int L) {
   return -1;
 }
 
-// Threads per workgroup of the patch kernel and of the apply kernel, by degree.
-constexpr int patch_threads(int p) { return p <= 2 ? 64 : (p <= 4 ? 128 : 256); }
+// Threads per workgroup of the patch kernel and of the apply kernel, by degree.  3D patches
+// of degree >= 7 fit one or two per CU in LDS (FP64 / FP32), so they get 8 waves, over which
+// the contraction stages split their outputs.
+constexpr int patch_threads(int p, int dim = 3) { return p <= 2 ? 64 : (p <= 4 ? 128 : (p <= 6 || dim == 2 ? 256 : 512)); }
 constexpr int apply_threads(int p) { return p <= 2 ? 128 : 128; }
 
 // Lanes per patch and per cell of the general (metric) path: FP64 patches of degree >= 5

@@ -177,8 +177,8 @@ struct EmuSmooth {
       switch (lanes) {
         case 0: return o ? go<1, true>(base, n, color_dir, local_only, n_blocks)
                          : go<1, false>(base, n, color_dir, local_only, n_blocks);
-        case 1: return o ? go<patch_threads(P), true>(base, n, color_dir, local_only, n_blocks)
-                         : go<patch_threads(P), false>(base, n, color_dir, local_only, n_blocks);
+        case 1: return o ? go<patch_threads(P, DIM), true>(base, n, color_dir, local_only, n_blocks)
+                         : go<patch_threads(P, DIM), false>(base, n, color_dir, local_only, n_blocks);
         case 2: return o ? go<256, true>(base, n, color_dir, local_only, n_blocks)
                          : go<256, false>(base, n, color_dir, local_only, n_blocks);
         default: return -1;

@@ -4,7 +4,7 @@
         per-kernel totals and averages from a --kernel-trace run (CSV output under DIR)
     python -m paper_2512_02577_amd.rocprof_summary traffic --trace DIR --fetch DIR --write DIR
                                                           --kernel REGEX --name NAME [--grid G ...]
-                                                          [--bytes B] [--record]
+                                                          [--bytes B] [--record] [--summary PATH]
         average duration and HBM traffic per dispatch of the matching kernel (grouped by grid
         size, the groups listed by --grid), FETCH_SIZE and WRITE_SIZE scaled by what the same
         counters read for the largest plain device copy in the run (a blit of known size:
@@ -144,7 +144,7 @@ def traffic(args) -> int:
         rec.update({"kernel": args.kernel, "method": f"FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two "
                     f"rocprofv3 --pmc runs, each scaled by the same counter on the largest plain device copy "
                     f"of the run ({copy_bytes} B read and written): FETCH x {sf:.4f}, WRITE x {sw:.4f}",
-                    "summary": f"profiles/{args.name}.md",
+                    "summary": args.summary or f"profiles/{args.name}.md",
                     "sources_sha256": {rel: hashlib.sha256(_source(rel, args.git_rev)).hexdigest()
                                        for rel in KERNEL_SOURCES}})
         with open(os.path.join(ROOT, "profiles", f"{args.name}.traffic.json"), "w") as fh:
@@ -168,6 +168,7 @@ def main(argv=None) -> int:
     f.add_argument("--bytes", type=str, default="", help="algorithmic bytes per launch by grid: g1=b1,g2=b2")
     f.add_argument("--copy-bytes", type=int, default=2 ** 30)
     f.add_argument("--record", action="store_true")
+    f.add_argument("--summary", default=None, help="the profile summary the record belongs to (default profiles/NAME.md)")
     f.add_argument("--git-rev", default=None, help="hash the kernel sources of this revision (the profiled build)")
     args = ap.parse_args(argv)
     if args.cmd == "trace":

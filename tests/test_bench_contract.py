@@ -20,8 +20,8 @@ def test_bench_refuses_more_than_one_gpu():
 def test_traffic_records_are_well_formed():
     # the records bench.py reads: HBM bytes per launch of the smoother color launch and of the
     # apply at 64^3 and 128^3 Q4, each naming its summary and the kernel sources it was taken with
-    for name in ("k_smooth_fp64_q4_64cube", "k_smooth_fp64_q4_128cube", "k_apply_fp64_q4_64cube",
-                 "k_apply_fp64_q4_128cube"):
+    for name in ("k_smooth_fp64_q4_64cube", "k_smooth_fp64_q4_128cube", "k_march_fp64_q4_64cube",
+                 "k_march_fp64_q4_128cube", "k_march_fp64_q8_64cube"):
         rec = json.load(open(os.path.join(ROOT, "profiles", name + ".traffic.json")))
         assert rec["fetch_bytes_per_launch"] > 0 and rec["write_bytes_per_launch"] > 0
         for rel in rec["sources_sha256"]:
