@@ -6,7 +6,11 @@ points, and the exact coarse solve.
 couples several cells plus a seeded sample) with the assembled operator of eq. matrix,
 which is pinned independently in test_oracle_operator.py (closed forms, exactness,
 symmetry); a planted mistake in its candidate-cell set must make the comparison fail.
-`quadrature_points` is compared with Gauss-Legendre points written in closed form.
+`quadrature_points` is compared with Gauss-Legendre points written in closed form.  The
+consistent mass matrix (the right-hand side b = M f of the benchmark, and the reference of the
+GPU's mass apply) is pinned by its row sums (the integrals of the basis functions: products of
+Gauss-Lobatto weights, computed here from their closed form), symmetry and definiteness, and
+the textbook Q1 matrix.
 """
 import itertools
 
@@ -127,3 +131,53 @@ def test_coarse_solve_inverts_the_coarse_operator(dim, n, p, jit):
     z = pb.coarse_solve(r)
     A0 = stiffness_matrix(pb.meshes[0], p)
     assert abs(A0 @ z - r).max() <= 1e-12 * abs(r).max()
+
+
+def _gll_weights_unit(p):
+    """Gauss-Lobatto weights on [0, 1] in closed form: nodes -1, 1 and the roots of P_p',
+    weights 2 / (p (p + 1) P_p(x)^2) on [-1, 1] (independent of the oracle's quadrature)."""
+    from numpy.polynomial import legendre as L
+
+    c = np.zeros(p + 1)
+    c[p] = 1.0
+    x = np.concatenate([[-1.0], np.sort(np.real(L.legroots(L.legder(c)))), [1.0]]) if p > 1 else np.array([-1.0, 1.0])
+    w = 2.0 / (p * (p + 1) * L.legval(x, c) ** 2)
+    return w / 2.0
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 3, 1), (2, 2, 3), (2, 3, 5), (3, 2, 2), (3, 2, 4), (2, 2, 8)])
+def test_mass_matrix_row_sums_are_integrals_of_the_basis(dim, n, p):
+    # the nodal basis sums to one, so a row sum of the consistent mass matrix is the integral
+    # of that basis function: on the uniform mesh the product over the directions of h times
+    # the Gauss-Lobatto weights of the (one or two) cells containing the node's coordinate
+    # (the Lobatto rule with p+1 points integrates the degree-p basis exactly)
+    M = asm.mass_matrix(StructuredMesh(dim, n), p)
+    m = p * n + 1
+    w = _gll_weights_unit(p) / n
+    w1 = np.zeros(m)
+    for c in range(n):
+        w1[p * c:p * c + p + 1] += w
+    ref = w1
+    for _ in range(dim - 1):
+        ref = np.multiply.outer(w1, ref).reshape(-1)  # x fastest: the last factor varies fastest
+    assert abs(M.sum(axis=1).A1 - ref).max() <= 1e-14
+    assert abs(M.sum() - 1.0) <= 1e-13  # the unit box's volume
+
+
+@pytest.mark.parametrize("dim,n,p,jit", [(2, 3, 3, 0.0), (3, 2, 2, 0.0), (2, 3, 2, 0.2)])
+def test_mass_matrix_is_symmetric_positive_definite(dim, n, p, jit):
+    M = asm.mass_matrix(_mesh(dim, n, jit), p).toarray()
+    assert abs(M - M.T).max() <= 1e-15 * abs(M).max()
+    assert np.linalg.eigvalsh(M).min() > 0
+
+
+def test_mass_matrix_of_q1_is_the_textbook_kronecker_product():
+    # Q1 on a uniform 1D mesh of n cells: h/6 tridiag(1, 4, 1) (2 h/6 at the ends); the 2D
+    # matrix is the Kronecker product of two 1D ones
+    n = 4
+    h = 1.0 / n
+    M1 = np.diag(np.full(n + 1, 4.0)) + np.diag(np.ones(n), 1) + np.diag(np.ones(n), -1)
+    M1[0, 0] = M1[n, n] = 2.0
+    M1 *= h / 6
+    M = asm.mass_matrix(StructuredMesh(2, n), 1).toarray()
+    assert abs(M - np.kron(M1, M1)).max() <= 1e-15
