@@ -18,8 +18,9 @@ namespace pmg {
 constexpr int kBatchMax = 16;
 constexpr int kBatchThreads = 256;  // workgroup size of the batched transfer kernel
 
-// Apply tile (cells per direction) of option `opt` for degree p: 0 is the default of the
-// single-problem kernel, 1 one cell fewer (smaller LDS tile, more workgroups per CU).
+// Apply option of a degree: 0 the marching apply of the single-problem path; 1 the owned-node
+// tile apply with batch_tile(p, 1) cells per direction (its own tables).  batch_tile(p, 0)
+// is the single-problem tile size.
 constexpr int batch_tile(int p, int opt) {
   return opt == 0 ? tile_cells(p) : (tile_cells(p) > 1 ? tile_cells(p) - 1 : 1);
 }

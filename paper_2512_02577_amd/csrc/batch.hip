@@ -48,8 +48,8 @@ __device__ inline int opaque_tid() {
 // One kernel per degree: the patch body of the single-problem kernel (same threads per
 // workgroup, same registers) inside a loop over the work items of every segment.
 template <typename T, int P>
-__global__ __launch_bounds__(patch_threads(P)) void k_bsmooth(const BSmoothStage<T> *st_) {
-  using B = PatchBody<3, T, patch_threads(P), P, typename PaperH<P>::type>;
+__global__ __launch_bounds__(patch_threads(P, 3, sizeof(T))) void k_bsmooth(const BSmoothStage<T> *st_) {
+  using B = PatchBody<3, T, patch_threads(P, 3, sizeof(T)), P, typename PaperH<P>::type>;
   const cptr<BSmoothStage<T>> st = as_const(st_);
   T *lds = lds_arena<T>();
   const int nseg = st->nseg, total = st->total;
@@ -58,11 +58,33 @@ __global__ __launch_bounds__(patch_threads(P)) void k_bsmooth(const BSmoothStage
     if (!as_const(st->active)[st->seg[s].prob]) continue;
     const int local = blk - st->seg[s].start;
     if (local >= st->seg[s].a.n_patch) continue;  // padding of the segment to a multiple of 8
-    B::smooth_patch(opaque_tid<patch_threads(P)>(), local, lds, table_ref(st->seg[s].a));
+    B::smooth_patch(opaque_tid<patch_threads(P, 3, sizeof(T))>(), local, lds, table_ref(st->seg[s].a));
     __syncthreads();
   }
 }
 
+template <typename T, int P, bool RESID>
+using BMarch = MarchBody<T, march_threads(P), P, march_tile(P), march_tile_y(P), march_group(P),
+                         P * (tile_cells(P) + 1) + 1, RESID, false>;
+
+// The marching apply of each segment's problem (apply option 0).
+template <typename T, int P, bool RESID>
+__global__ __launch_bounds__(march_threads(P)) void k_bmarch(const BApplyStage<T> *st_) {
+  using B = BMarch<T, P, RESID>;
+  const cptr<BApplyStage<T>> st = as_const(st_);
+  T *lds = lds_arena<T>();
+  const int nseg = st->nseg, total = st->total;
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int s = seg_of(st, nseg, blk);
+    if (!as_const(st->active)[st->seg[s].prob]) continue;
+    const int local = blk - st->seg[s].start;
+    if (local >= st->seg[s].a.n_tiles) continue;  // padding of the segment to a multiple of 8
+    B::run(opaque_tid<march_threads(P)>(), local, lds, table_ref(st->seg[s].a));
+    __syncthreads();
+  }
+}
+
+// The owned-node tile apply (apply option 1).
 template <typename T, int P, int OPT, bool RESID>
 __global__ __launch_bounds__(apply_threads(P)) void k_bapply(const BApplyStage<T> *st_) {
   using B = ApplyBody<3, T, apply_threads(P), P, batch_tile(P, OPT), RESID>;
@@ -154,7 +176,7 @@ struct SmoothBytes {
   template <int P>
   struct F {
     static int run(int n_iter, size_t *o) {
-      *o = PatchBody<3, T, patch_threads(P), P, typename PaperH<P>::type>::arena(n_iter) * sizeof(T);
+      *o = PatchBody<3, T, patch_threads(P, 3, sizeof(T)), P, typename PaperH<P>::type>::arena(n_iter) * sizeof(T);
       return 0;
     }
   };
@@ -165,8 +187,7 @@ struct ApplyBytes {
   template <int P>
   struct F {
     static int run(int opt, size_t *o) {
-      *o = (opt == 0 ? ApplyBody<3, T, apply_threads(P), P, batch_tile(P, 0), false>::size
-                     : ApplyBody<3, T, apply_threads(P), P, batch_tile(P, 1), false>::size) *
+      *o = (opt == 0 ? BMarch<T, P, false>::size : ApplyBody<3, T, apply_threads(P), P, batch_tile(P, 1), false>::size) *
            sizeof(T);
       return 0;
     }
@@ -292,8 +313,8 @@ struct KernelTable {
   struct F {
     static int run(const void **sm, const void **ap) {
       *sm = (const void *)k_bsmooth<T, P>;
-      ap[0] = (const void *)k_bapply<T, P, 0, false>;
-      ap[1] = (const void *)k_bapply<T, P, 0, true>;
+      ap[0] = (const void *)k_bmarch<T, P, false>;
+      ap[1] = (const void *)k_bmarch<T, P, true>;
       ap[2] = (const void *)k_bapply<T, P, 1, false>;
       ap[3] = (const void *)k_bapply<T, P, 1, true>;
       return 0;
@@ -319,7 +340,7 @@ int BatchLaunch<T>::smooth(const BSmoothStage<T> *st, int p, int grid, size_t sh
   const void *sm = nullptr, *ap[4] = {};
   if (dispatch_degree<KernelTable<T>::template F>(p, &sm, ap) != 0) return -2;
   void *args[] = {(void *)&st};
-  if (hipLaunchKernel(sm, dim3(grid), dim3(patch_threads(p)), args, shmem, s) != hipSuccess) return -4;
+  if (hipLaunchKernel(sm, dim3(grid), dim3(patch_threads(p, 3, sizeof(T))), args, shmem, s) != hipSuccess) return -4;
   return 0;
 }
 
@@ -330,8 +351,8 @@ int BatchLaunch<T>::apply(const BApplyStage<T> *st, int p, int tile, bool resid,
   const void *sm = nullptr, *ap[4] = {};
   if (dispatch_degree<KernelTable<T>::template F>(p, &sm, ap) != 0) return -2;
   void *args[] = {(void *)&st};
-  if (hipLaunchKernel(ap[2 * (tile != 0) + (resid ? 1 : 0)], dim3(grid), dim3(apply_threads(p)), args, shmem, s) !=
-      hipSuccess)
+  const int threads = tile != 0 ? apply_threads(p) : march_threads(p);
+  if (hipLaunchKernel(ap[2 * (tile != 0) + (resid ? 1 : 0)], dim3(grid), dim3(threads), args, shmem, s) != hipSuccess)
     return -4;
   return 0;
 }

@@ -264,14 +264,20 @@ struct Builder {
     for (auto [i, l] : parts) {
       pmg_problem *pr = bt->pr[i];
       const int p = pr->p, opt = pl.tune.tile[p];
-      const int tc = batch_tile(p, opt);
       ApplyArgs<T> a{};
       a.Kt = opt ? alt_kt<T>(bt, i) : pr->pd<T>().tabs.Kt;
       a.Mt = opt ? alt_mt<T>(bt, i) : pr->pd<T>().tabs.Mt;
       a.c = (T)pr->cscale(l);
       a.n = pr->sizes[l];
-      a.ntile = (a.n + tc - 1) / tc;
-      a.n_tiles = a.ntile * a.ntile * a.ntile;
+      if (opt == 0) {  // the marching apply, with the single-problem launch geometry
+        int nz;
+        march_geometry(a.n, march_tile(p), march_tile_y(p), kMarchBlocks, a.mt, a.mty, nz, a.zc);
+        a.n_tiles = a.mt * a.mty * nz;
+      } else {
+        const int tc = batch_tile(p, opt);
+        a.ntile = (a.n + tc - 1) / tc;
+        a.n_tiles = a.ntile * a.ntile * a.ntile;
+      }
       if (resid) {
         a.u = vec_z<T>(pr, l);
         a.b = vec_r<T>(pr, l);
@@ -603,7 +609,7 @@ std::vector<Knob> knobs(pmg_batch *bt, Plan<T> &pl, bool outer) {
     if (!deg[p]) continue;
     const std::string d = "/p" + std::to_string(p);
     if (!outer) k.push_back({"smooth_wpc" + d, &pl.tune.smooth_wpc[p], wpc, nullptr, false});
-    if (batch_tile(p, 1) != batch_tile(p, 0) && BatchLaunch<T>::apply_bytes(p, 1) <= bt->lds_max)
+    if (BatchLaunch<T>::apply_bytes(p, 1) <= bt->lds_max)
       k.push_back({"apply_tile" + d, &pl.tune.tile[p], {0, 1}, nullptr, true});
     k.push_back({"apply_wpc" + d, &pl.tune.apply_wpc[p], wpc, nullptr, false});
   }

@@ -70,9 +70,11 @@ inline int hierarchy_code(int p, const int *deg, int L) {
 }
 
 // Threads per workgroup of the patch kernel and of the apply kernel, by degree.  3D patches
-// of degree >= 7 fit one or two per CU in LDS (FP64 / FP32), so they get 8 waves, over which
+// that fit at most two per CU in LDS (degree 8, and degree 7 in FP64) get 8 waves, over which
 // the contraction stages split their outputs.
-constexpr int patch_threads(int p, int dim = 3) { return p <= 2 ? 64 : (p <= 4 ? 128 : (p <= 6 || dim == 2 ? 256 : 512)); }
+constexpr int patch_threads(int p, int dim = 3, int tbytes = 8) {
+  return p <= 2 ? 64 : (p <= 4 ? 128 : (p <= 6 || dim == 2 || (p == 7 && tbytes < 8) ? 256 : 512));
+}
 constexpr int apply_threads(int p) { return p <= 2 ? 128 : 128; }
 
 // Lanes per patch and per cell of the general (metric) path: FP64 patches of degree >= 5

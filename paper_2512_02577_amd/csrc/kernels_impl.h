@@ -24,8 +24,8 @@ __device__ inline T *lds_arena() {
 // ---- patch smoother: one workgroup per patch of one color ----
 // ONE: the local solver is one half V-cycle (no post-smoothing, one Richardson step).
 template <int DIM, typename T, int P, class H, bool ONE>
-__global__ __launch_bounds__(patch_threads(P, DIM)) void k_smooth(SmoothArgs<T> a) {
-  using B = PatchBody<DIM, T, patch_threads(P, DIM), P, H>;
+__global__ __launch_bounds__(patch_threads(P, DIM, sizeof(T))) void k_smooth(SmoothArgs<T> a) {
+  using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
   B::template smooth_patch<ONE>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
@@ -39,8 +39,8 @@ __global__ __launch_bounds__(256) void k_smooth_w(SmoothArgs<T> a) {
 }
 
 template <int DIM, typename T, int P, class H>
-__global__ __launch_bounds__(patch_threads(P, DIM)) void k_smooth_g(SmoothArgs<T> a, void *garena) {
-  using B = PatchBody<DIM, T, patch_threads(P, DIM), P, H>;
+__global__ __launch_bounds__(patch_threads(P, DIM, sizeof(T))) void k_smooth_g(SmoothArgs<T> a, void *garena) {
+  using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
   T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
   for (int blk = blockIdx.x; blk < a.n_patch; blk += gridDim.x) {
     B::smooth_patch(threadIdx.x, blk, ar, a);
@@ -49,14 +49,14 @@ __global__ __launch_bounds__(patch_threads(P, DIM)) void k_smooth_g(SmoothArgs<T
 }
 
 template <int DIM, typename T, int P, class H>
-__global__ __launch_bounds__(patch_threads(P, DIM)) void k_local(SmoothArgs<T> a, int n_blocks) {
-  using B = PatchBody<DIM, T, patch_threads(P, DIM), P, H>;
+__global__ __launch_bounds__(patch_threads(P, DIM, sizeof(T))) void k_local(SmoothArgs<T> a, int n_blocks) {
+  using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
   B::local_only(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
 template <int DIM, typename T, int P, class H>
-__global__ __launch_bounds__(patch_threads(P, DIM)) void k_local_g(SmoothArgs<T> a, int n_blocks, void *garena) {
-  using B = PatchBody<DIM, T, patch_threads(P, DIM), P, H>;
+__global__ __launch_bounds__(patch_threads(P, DIM, sizeof(T))) void k_local_g(SmoothArgs<T> a, int n_blocks, void *garena) {
+  using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
   T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
   for (int blk = blockIdx.x; blk < n_blocks; blk += gridDim.x) {
     B::local_only(threadIdx.x, blk, ar, a);
@@ -136,21 +136,21 @@ struct SmoothL {
     template <int P, class H>
     struct F {
       static int run(const SmoothArgs<T> &a, const Arena &ar, hipStream_t s) {
-        using B = PatchBody<DIM, T, patch_threads(P, DIM), P, H>;
+        using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
         const size_t bytes = B::arena(a.n_iter) * sizeof(T);
         const bool one = a.full == 0 && a.n_iter == 1 && a.direct == 0 && a.reinf == 0;
         // patch_lanes: 0 by launch size, 1 always the per-degree count, 2 always 256
         const bool wide = ar.patch_lanes == 2 || (ar.patch_lanes == 0 && a.n_patch <= kWideLaunch * ar.ncu);
-        if constexpr (patch_threads(P, DIM) < 256)
+        if constexpr (patch_threads(P, DIM, sizeof(T)) < 256)
           if (wide && bytes <= ar.lds_max)
             return one ? launch_arena(k_smooth_w<DIM, T, P, H, true>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256,
                                       bytes, ar, s, a)
                        : launch_arena(k_smooth_w<DIM, T, P, H, false>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256,
                                       bytes, ar, s, a);
         return one ? launch_arena(k_smooth<DIM, T, P, H, true>, k_smooth_g<DIM, T, P, H>, a.n_patch,
-                                  patch_threads(P, DIM), bytes, ar, s, a)
+                                  patch_threads(P, DIM, sizeof(T)), bytes, ar, s, a)
                    : launch_arena(k_smooth<DIM, T, P, H, false>, k_smooth_g<DIM, T, P, H>, a.n_patch,
-                                  patch_threads(P, DIM), bytes, ar, s, a);
+                                  patch_threads(P, DIM, sizeof(T)), bytes, ar, s, a);
       }
     };
   };
@@ -163,8 +163,8 @@ struct LocalL {
     template <int P, class H>
     struct F {
       static int run(const SmoothArgs<T> &a, int nb, const Arena &ar, hipStream_t s) {
-        using B = PatchBody<DIM, T, patch_threads(P, DIM), P, H>;
-        return launch_arena(k_local<DIM, T, P, H>, k_local_g<DIM, T, P, H>, nb, patch_threads(P, DIM),
+        using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
+        return launch_arena(k_local<DIM, T, P, H>, k_local_g<DIM, T, P, H>, nb, patch_threads(P, DIM, sizeof(T)),
                             B::arena(a.n_iter) * sizeof(T), ar, s, a, nb);
       }
     };
@@ -176,7 +176,7 @@ struct SizeL {
   template <int P, class H>
   struct F {
     static int run(size_t *out) {
-      *out = PatchBody<DIM, T, patch_threads(P, DIM), P, H>::size * sizeof(T);
+      *out = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>::size * sizeof(T);
       return 0;
     }
   };
