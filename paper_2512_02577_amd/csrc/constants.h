@@ -9,12 +9,13 @@ constexpr int tile_cells(int p) { return p == 1 ? 8 : p == 2 ? 4 : p == 3 ? 3 : 
 
 // xy tile (TX x TY cells), planes per group (G) and lanes of the 3D operator apply that
 // marches in z, by degree.  The xy input (tile and one halo cell per side) has 289 to 625 z
-// columns, one or two per lane; the y and x contractions run on G of a layer's P planes at
-// a time.  Tile and group are sized so that the LDS of a workgroup (two fields of G planes of
-// the input and of the y-contracted tile) lets two to four workgroups share a CU in FP64.
+// columns, one per lane (two at p <= 4 on 256 lanes); the y and x contractions run on G of a
+// layer's P planes at a time.  Degrees <= 4 fit three or four workgroups per CU in FP64; from
+// degree 6 on the registers of the z window allow only one or two per CU whatever the LDS,
+// so the whole layer is one group (fewer barriers per layer).
 constexpr int march_tile(int p) { return p == 1 ? 16 : p == 2 ? 8 : p == 3 ? 5 : p == 4 ? 4 : p == 5 ? 3 : 2; }
 constexpr int march_tile_y(int p) { return p == 1 ? 16 : p == 2 ? 8 : p == 3 ? 5 : p == 4 ? 3 : p == 5 ? 3 : 2; }
-constexpr int march_group(int p) { return p <= 5 ? p : (p == 6 ? 3 : 4); }
+constexpr int march_group(int p) { return p; }
 constexpr int march_threads(int p) { return p <= 4 ? 256 : p == 5 ? 512 : p == 6 ? 384 : p == 7 ? 512 : 640; }
 // Workgroups a marching apply aims for (the z segments get shorter until it has them).
 constexpr int kMarchBlocks = 4096;

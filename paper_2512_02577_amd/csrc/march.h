@@ -18,6 +18,9 @@
 //
 // Order of the contractions (any order gives the same operator): Zm = Mz u, Zk = Kz u;
 // Ym = My Zm, Yg = Ky Zm + My Zk; v = c (Kx Ym + Mx Yg).  Mass: Zm, Ym = My Zm, v = c Mx Ym.
+// A y or x unit reads its first field, starts the FMA chains of its outputs, then reads the
+// second field into the same registers and continues them: half the input registers of
+// reading both at once (the register count, not the LDS, sets the occupancy from p = 6 on).
 #pragma once
 
 namespace pmg {
@@ -48,7 +51,7 @@ struct CellRows {
   }
 };
 
-// Row o of M v, and of K va + M vb, as one FMA chain each
+// Row o of M v as one FMA chain
 template <class R, int P, typename T, class MP>
 PMG_INLINE T cell_row1(const MP &M, int o, const T *v) {
   const int l = R::lo(o);
@@ -58,17 +61,13 @@ PMG_INLINE T cell_row1(const MP &M, int o, const T *v) {
     if (t > l) acc += M[R::idx(o, t)] * v[t];
   return acc;
 }
+// acc + row o of M v, continuing acc's FMA chain
 template <class R, int P, typename T, class MP>
-PMG_INLINE T cell_row2(const MP &K, const MP &M, int o, const T *va, const T *vb) {
+PMG_INLINE T cell_row_add(const MP &M, int o, const T *v, T acc) {
   const int l = R::lo(o);
-  T acc = K[R::idx(o, l)] * va[l];
-  acc += M[R::idx(o, l)] * vb[l];
 #pragma unroll
   for (int t = 0; t <= 2 * P; ++t)
-    if (t > l) {
-      acc += K[R::idx(o, t)] * va[t];
-      acc += M[R::idx(o, t)] * vb[t];
-    }
+    if (t >= l) acc += M[R::idx(o, t)] * v[t];
   return acc;
 }
 
@@ -229,16 +228,20 @@ struct MarchBody {
         for (int v = tid; v < NIX * TY * GG; v += NT) {
           const int i = v % NIX, cy = (v / NIX) % TY, o = v / (NIX * TY);
           const int ib = o * NC + P * cy * NIX + i, ob = o * NOY * NIX + P * cy * NIX + i;
-          T za[W], zb[MASS ? 1 : W];
+          T za[W], acc[MASS ? 1 : P];
 #pragma unroll
-          for (int tz = 0; tz < W; ++tz) {
-            za[tz] = zm[ib + tz * NIX];
-            if constexpr (!MASS) zb[tz] = zk[ib + tz * NIX];
-          }
+          for (int tz = 0; tz < W; ++tz) za[tz] = zm[ib + tz * NIX];
 #pragma unroll
           for (int oy = 0; oy < P; ++oy) {
             ym[ob + oy * NIX] = cell_row1<R, P>(M0, oy, za);
-            if constexpr (!MASS) yg[ob + oy * NIX] = cell_row2<R, P>(K0, M0, oy, za, zb);
+            if constexpr (!MASS) acc[oy] = cell_row1<R, P>(K0, oy, za);
+          }
+          if constexpr (!MASS) {
+            // the second field after the first is dead: its registers take the window
+#pragma unroll
+            for (int tz = 0; tz < W; ++tz) za[tz] = zk[ib + tz * NIX];
+#pragma unroll
+            for (int oy = 0; oy < P; ++oy) yg[ob + oy * NIX] = cell_row_add<R, P>(M0, oy, za, acc[oy]);
           }
         }
         PMG_SYNC();
@@ -246,17 +249,19 @@ struct MarchBody {
         for (int v = tid; v < NOY * TX * GG; v += NT) {
           const int jo = v % NOY, cx = (v / NOY) % TX, o = v / (NOY * TX);
           const int ib = o * NOY * NIX + jo * NIX + P * cx;
-          T ya[W], yb[MASS ? 1 : W];
+          T ya[W], acc[P];
 #pragma unroll
-          for (int tz = 0; tz < W; ++tz) {
-            ya[tz] = ym[ib + tz];
-            if constexpr (!MASS) yb[tz] = yg[ib + tz];
+          for (int tz = 0; tz < W; ++tz) ya[tz] = ym[ib + tz];
+#pragma unroll
+          for (int ox = 0; ox < P; ++ox) acc[ox] = MASS ? cell_row1<R, P>(M0, ox, ya) : cell_row1<R, P>(K0, ox, ya);
+          if constexpr (!MASS) {
+#pragma unroll
+            for (int tz = 0; tz < W; ++tz) ya[tz] = yg[ib + tz];
+#pragma unroll
+            for (int ox = 0; ox < P; ++ox) acc[ox] = cell_row_add<R, P>(M0, ox, ya, acc[ox]);
           }
 #pragma unroll
-          for (int ox = 0; ox < P; ++ox) {
-            const T acc = MASS ? cell_row1<R, P>(M0, ox, ya) : cell_row2<R, P>(K0, M0, ox, ya, yb);
-            ost[o * NOY * OS + jo * OS + P * cx + ox] = a.c * acc;
-          }
+          for (int ox = 0; ox < P; ++ox) ost[o * NOY * OS + jo * OS + P * cx + ox] = a.c * acc[ox];
         }
         PMG_SYNC();
         if (g == NG - 1) {
