@@ -69,11 +69,12 @@ inline int hierarchy_code(int p, const int *deg, int L) {
   return -1;
 }
 
-// Threads per workgroup of the patch kernel and of the apply kernel, by degree.  3D patches
-// that fit at most two per CU in LDS (degree 8, and degree 7 in FP64) get 8 waves, over which
-// the contraction stages split their outputs.
+// Threads per workgroup of the patch kernel and of the apply kernel, by degree.  Up to degree
+// 3 one wave per patch (its stages have at most 49 pencils); 3D patches that fit at most two
+// per CU in LDS (degree 8, and degree 7 in FP64) get 8 waves, over which the contraction
+// stages split their outputs.
 constexpr int patch_threads(int p, int dim = 3, int tbytes = 8) {
-  return p <= 2 ? 64 : (p <= 4 ? 128 : (p <= 6 || dim == 2 || (p == 7 && tbytes < 8) ? 256 : 512));
+  return p <= 3 ? 64 : (p <= 4 ? 128 : (p <= 6 || dim == 2 || (p == 7 && tbytes < 8) ? 256 : 512));
 }
 constexpr int apply_threads(int p) { return p <= 2 ? 128 : 128; }
 
