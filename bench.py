@@ -15,8 +15,9 @@ with the fused local p-multigrid, residuals, transfers, coarse solve, dot produc
 whole path).  value = nodes x V-cycles / time (DoF/s per V-cycle).  Beside it:
   * the same solve with FP32 multigrid inside the FP64 CG (time to solution, iterations);
   * per-call rates (apply, one smoother application, one V-cycle) with HIP events on the
-    launch stream, and the roofline of the dominant kernel (the finest-level smoother color
-    launch) and of the operator apply;
+    launch stream (mean over back-to-back calls; per call mean and median, with warm caches
+    and after a 512 MB flush write), and the roofline of the dominant kernel (the
+    finest-level smoother color launch) and of the operator apply;
   * the degree sweep p = 2..8 at 64^3 (FP64-MG and FP32-MG time to 1e-8, iterations);
   * 128^3 Q4 (135M nodes, working set far beyond the 256 MB last-level cache): apply and
     smoother rates;
@@ -64,6 +65,28 @@ def time_events(fn, reps, torch):
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def time_calls(fn, reps, torch, flush=None):
+    """Per-call milliseconds of fn() with HIP events around each call on the current stream:
+    (mean, median).  With `flush` (a 512 MB device buffer) the buffer is written between the
+    calls, outside the timed events, so that every call starts with the last-level cache
+    holding none of its data."""
+    import statistics
+
+    s = torch.cuda.current_stream()
+    fn()
+    ts = []
+    for _ in range(reps):
+        if flush is not None:
+            flush.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return {"mean_ms": sum(ts) / len(ts), "median_ms": statistics.median(ts)}
 
 
 def measured_traffic(name):
@@ -389,6 +412,16 @@ def kernel_rates(torch, pmg, perfmodel, np, pr, dim, n, p, reps):
               "achieved_tflops": flops / ncol / t_launch / 1e12,
               "fp32_avg_launch_us": t_smooth32 / ncol * 1e3,
               "fp32_achieved_gbs": bytes_launches / 2 / ncol / (t_smooth32 / ncol * 1e-3) / 1e9}
+    # per-call statistics, with the caches warm and after a 512 MB flush write
+    flush = torch.empty(2 ** 26, dtype=torch.float64, device=dev)
+    z = torch.empty_like(u)
+    rec["per_call"] = {}
+    for name, fn in (("apply_fp64", lambda: pmg.apply_operator(pr, L, u, v)),
+                     ("smooth_fp64", lambda: pmg.smooth(pr, L, u_s, b, 1)),
+                     ("vcycle_fp64", lambda: pmg.vcycle(pr, b, z, pmg.FP64))):
+        warm, cold = time_calls(fn, 10, torch), time_calls(fn, 10, torch, flush)
+        rec["per_call"][name] = {**warm, "flushed_mean_ms": cold["mean_ms"], "flushed_median_ms": cold["median_ms"]}
+    del flush, z
     apply_bytes = perfmodel.apply_bytes(dim, n, p)
     apply = {"avg_launch_us": t_apply * 1e3, "bytes_per_launch": apply_bytes,
              "achieved_gbs": apply_bytes / (t_apply * 1e-3) / 1e9,
@@ -558,6 +591,7 @@ def main():
         "dof_per_s": rates["dof_per_s"],
         "ms": rates["ms"],
         "smooth_over_apply": rates["smooth_over_apply"],
+        "per_call": rates["per_call"],
         "roofline": roof,
         "roofline_operator": roof_apply,
     }
