@@ -386,39 +386,83 @@ struct PatchBody {
         uold[k] = u_in[interior_index(e < nd ? e : nd - 1, g0, m)];
       }
     }
-    // closure of u (zero on the Dirichlet boundary; every closure node lies inside the
-    // mesh, so the load itself is always valid) and the interior of b
     const T *__restrict__ b_in = a.b;
-    lane_gather2<Nd, nd, NT, 16, T>(
-        tid,
-        [&](int e) {
-          const int i = e % N, j = (e / N) % N, k = DIM == 3 ? e / (N * N) : 0;
-          const int gx = g0[0] + i, gy = g0[1] + j, gz = g0[2] + k;
-          bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
-          if (DIM == 3) bnd = bnd || gz == 0 || gz == m - 1;
-          const T x = u_in[gx + m * (gy + m * gz)];
-          return bnd ? T(0) : x;
-        },
-        [&](int e, T x) { ucl[e] = x; }, [&](int e) { return b_in[interior_index(e, g0, m)]; },
-        [&](int e, T x) { r[e] = x; });
-    PMG_SYNC();
-    // r = b - c (sum_k Kr_k (x) Mr_others) ubar   (closure -> interior)
-    {
-      using Pat = PatResidual<P>;
+    using Pat = PatResidual<P>;
+    if constexpr (DIM == 3) {
+      // r = b - c (sum_k Kr_k (x) Mr_others) ubar, the z contraction first: a lane per closure
+      // column (i, j) loads its N nodes from global memory (zero on the Dirichlet boundary;
+      // every closure node lies inside the mesh, so the load is always valid) and writes
+      // Zm = Mr_z ubar and Zk = Kr_z ubar at the n interior planes; the closure itself never
+      // goes through LDS.  Then y (in place) and x (into r, on top of b).
+      T *Zm = ucl, *Zk = lds + off_B;
+      const cptr<T> Mr0 = as_const(a.tb.Mr), Kr0 = as_const(a.tb.Kr);
+      // the column as loaded; the Dirichlet mask is applied where it is used, so that the loads
+      // stay in flight over the gather of b
+      auto load_col = [&](int col, T *w) {
+        const T *cp = u_in + ((g0[0] + col % N) + m * ((g0[1] + col / N) + m * g0[2]));
+#pragma unroll
+        for (int k = 0; k < N; ++k) w[k] = cp[m * m * k];
+      };
+      auto zstage = [&](int col, T *w) {
+        const int gx = g0[0] + col % N, gy = g0[1] + col / N;
+        const bool bxy = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const int gz = g0[2] + k;
+          w[k] = (bxy || gz == 0 || gz == m - 1) ? T(0) : w[k];
+        }
+        const cptr<T> Mr = per_pencil(Mr0), Kr = per_pencil(Kr0);
+#pragma unroll
+        for (int o = 0; o < n; ++o) {
+          Zm[col + N * N * o] = row1<Pat>(Mr, o, w);
+          Zk[col + N * N * o] = row1<Pat>(Kr, o, w);
+        }
+      };
+      auto gather_b = [&]() {
+        lane_gather<nd, NT, 16, T>(
+            tid, [&](int e) { return b_in[interior_index(e, g0, m)]; }, [&](int e, T x) { r[e] = x; });
+      };
+      if constexpr (NT >= N * N) {
+        // one column per lane: its loads are in flight together with those of b
+        T w[N];
+        load_col(tid < N * N ? tid : N * N - 1, w);
+        gather_b();
+        if (tid < N * N) zstage(tid, w);
+      } else {
+        gather_b();
+        for (int col = tid; col < N * N; col += NT) {
+          T w[N];
+          load_col(col, w);
+          zstage(col, w);
+        }
+      }
+      PMG_SYNC();
+      scontract_pair<1, N, N, n, Pat, NT, Dense<N, N>, Dense<N, N>>(tid, Zm, Zk, a.tb.Mr, a.tb.Kr);
+      PMG_SYNC();
+      scontract_final<0, N, n, n, Pat, NT, Dense<N, N>, Dense<N, N>, Dense<n, n>>(tid, Zm, Zk, r, r, a.c, a.tb.Kr,
+                                                                                  a.tb.Mr);
+    } else {
+      // closure of u (zero on the Dirichlet boundary; every closure node lies inside the
+      // mesh, so the load itself is always valid) and the interior of b
+      lane_gather2<Nd, nd, NT, 16, T>(
+          tid,
+          [&](int e) {
+            const int i = e % N, j = e / N;
+            const int gx = g0[0] + i, gy = g0[1] + j;
+            const bool bnd = gx == 0 || gx == m - 1 || gy == 0 || gy == m - 1;
+            const T x = u_in[gx + m * gy];
+            return bnd ? T(0) : x;
+          },
+          [&](int e, T x) { ucl[e] = x; }, [&](int e) { return b_in[interior_index(e, g0, m)]; },
+          [&](int e, T x) { r[e] = x; });
+      PMG_SYNC();
+      // r = b - c (sum_k Kr_k (x) Mr_others) ubar   (closure -> interior)
       using DU = Dense<N, N>;
       using DB = Dense<n, N>;
       T *Bb = lds + off_B;
-      if constexpr (DIM == 3) {
-        scontract2<0, N, N, N, Pat, NT, DU, DU, DB, true>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
-        PMG_SYNC();
-        scontract_pair<1, n, N, N, Pat, NT, DU, DB>(tid, ucl, Bb, a.tb.Mr, a.tb.Kr);
-        PMG_SYNC();
-        scontract_final<2, n, n, N, Pat, NT, DU, DB, Dense<n, n>>(tid, ucl, Bb, r, r, a.c, a.tb.Kr, a.tb.Mr);
-      } else {
-        scontract2<0, N, N, 1, Pat, NT, DU, DU, DB, true>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
-        PMG_SYNC();
-        scontract_final<1, n, N, 1, Pat, NT, DU, DB, Dense<n, n>>(tid, ucl, Bb, r, r, a.c, a.tb.Kr, a.tb.Mr);
-      }
+      scontract2<0, N, N, 1, Pat, NT, DU, DU, DB, true>(tid, ucl, ucl, a.tb.Mr, Bb, a.tb.Kr);
+      PMG_SYNC();
+      scontract_final<1, n, N, 1, Pat, NT, DU, DB, Dense<n, n>>(tid, ucl, Bb, r, r, a.c, a.tb.Kr, a.tb.Mr);
     }
     PMG_SYNC();
     local_solve<ONE>(tid, lds, a, ONE ? &pre : nullptr);
