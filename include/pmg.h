@@ -309,6 +309,77 @@ int pmg_batch_solve(pmg_batch *bt, int mg_prec, const double *const *b, double *
 
 void pmg_destroy_batch(pmg_batch *bt);
 
+/* ------------------------------------------------------------------------------------
+ * General hexahedral (2D: quadrilateral) meshes with stored maps.
+ *
+ * Sec. 3 (implementation of the patch smoother): the cells forming each vertex patch are
+ * identified at setup, and a patch gathers, evaluates and scatters through its cells' DoF
+ * indices.  Sec. 4.4: the patches are colored with DSATUR so that no two patches of one
+ * color share a DoF whose update would race, and the smoother runs color by color.
+ *
+ * Vectors have one entry per node of the caller's numbering (n_dofs entries, float64 or
+ * float32 device pointers).  Homogeneous Dirichlet conditions hold on the nodes of faces
+ * that belong to one cell only; their rows are identity rows as on the structured box.
+ * Each cell is the multilinear image of the reference cell under its corners, and the
+ * operator is the same stored-metric sum factorization as the general path above.
+ * A vertex patch exists at every vertex on no boundary face; it must have 2^dim cells
+ * forming a 2x2(x2) block.  Patches are numbered by ascending vertex index; two patches
+ * conflict when they share a cell.  DSATUR (Brelaz 1979) colors the uncolored patch with
+ * the most distinct neighbour colors, ties to the most uncolored neighbours, then to the
+ * lowest index, with the smallest free color.  The apply adds cell contributions color by
+ * color over a DSATUR coloring of the cells (cells conflict when they share a vertex).
+ * Single h-level: the smoother and the operator; no h-hierarchy is built on these meshes.
+ * ------------------------------------------------------------------------------------ */
+typedef struct pmg_hex pmg_hex;
+
+/* Host-only setup from caller arrays (copied):
+ *   vertices       n_vertices * dim doubles, vertex-major.
+ *   cell_vertices  n_cells * 2^dim vertex indices, the cell's corners in its own
+ *                  lexicographic order (x fastest).
+ *   cell_dofs      n_cells * (degree+1)^dim node indices in [0, n_dofs), the cell's
+ *                  Gauss-Lobatto nodes in the same local order.
+ * Cells may be numbered, rotated and reflected arbitrarily: the library brings every
+ * face-connected set of cells into one common frame (mirrored if needed so that
+ * det J > 0) and permutes each cell's lists to it.  cfg: local_solver (half or full
+ * V-cycle), n_local_iter and omega are used; NULL for the defaults.  The p-hierarchy is
+ * the paper's (Sec. 2.2: 1, 3, 7, ... below the degree).  Errors: INVALID_ARG (indices out
+ * of range, a face shared by more than two cells, corners that are not a hexahedron,
+ * inverted or degenerate cells, a node map that differs on a shared face), UNSUPPORTED (a
+ * set of cells with no common orientation, an interior vertex without 2^dim cells, the
+ * direct or Cartesian-reinforced local solvers). */
+int pmg_setup_hex(int dim, int degree, int64_t n_vertices, const double *vertices, int64_t n_cells,
+                  const int32_t *cell_vertices, int64_t n_dofs, const int32_t *cell_dofs, const pmg_config *cfg,
+                  pmg_hex **out);
+
+/* Counts, the p-level degrees (coarsest first) and their Jacobi damping; any output may be
+ * NULL. */
+int pmg_hex_sizes(const pmg_hex *h, int64_t *n_patches, int *n_patch_colors, int *n_cell_colors, int *n_plevels,
+                  int32_t *degrees, double *omega);
+
+/* Copies of the stored maps (any output may be NULL): per patch its vertex, its color, its
+ * 2^dim cells (block position dx + 2 dy + 4 dz) and its (2 degree + 1)^dim closure nodes
+ * in the common frame (x fastest; -1 for Dirichlet nodes); per cell its color; per node 1
+ * on the Dirichlet boundary. */
+int pmg_hex_export(const pmg_hex *h, int32_t *patch_vertex, int32_t *patch_color, int32_t *patch_cells,
+                   int32_t *patch_closure, int32_t *cell_color, uint8_t *boundary);
+
+/* Device data on the current device: the maps, the metric of every p-level per Gauss point
+ * and the per-patch inverse diagonals.  The only call that allocates device memory. */
+int pmg_hex_device_init(pmg_hex *h);
+
+/* v = A u (identity rows on Dirichlet nodes); prec PMG_FP64 or PMG_FP32. */
+int pmg_hex_apply(pmg_hex *h, int prec, const void *u, void *v, void *stream);
+
+/* r = b - A u. */
+int pmg_hex_residual(pmg_hex *h, int prec, const void *b, const void *u, void *r, void *stream);
+
+/* One application of the vertex-patch smoother (Alg. 1, LocalSolve by Alg. 2 / Alg. 3 as
+ * on the structured box), colors ascending (color_dir = +1) or descending (-1), the
+ * patches of one color in parallel; u is updated in place. */
+int pmg_hex_smooth(pmg_hex *h, int prec, int color_dir, void *u, const void *b, void *stream);
+
+void pmg_hex_destroy(pmg_hex *h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,8 @@ HIP_SOURCES = ["kernels_metric_3d_f32.hip", "kernels_metric_3d_bf16.hip", "kerne
                "kernels_metric_2d_f64.hip", "kernels_metric_2d_f32.hip",
                "kernels_3d_f64.hip", "kernels_3d_f32.hip", "kernels_2d_f64.hip", "kernels_2d_f32.hip",
                "setup.hip", "blas.hip", "batch.hip", "capi.cpp", "batch_host.cpp", "kernels_dispatch.cpp",
-               "host_tables.cpp", "geometry.cpp"]
+               "host_tables.cpp", "geometry.cpp", "hex_setup.cpp", "hex_capi.cpp",
+               "kernels_hex_3d_f64.hip", "kernels_hex_3d_f32.hip", "kernels_hex_2d_f64.hip", "kernels_hex_2d_f32.hip"]
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
                # no packed FP32 instructions anywhere in the device code
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -56,7 +57,7 @@ def build_hip(jobs: int = 8, only: list[str] | None = None) -> str:
     cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src in ("capi.cpp", "batch_host.cpp", "kernels_dispatch.cpp") else []
+        lang = ["-x", "hip"] if src in ("capi.cpp", "batch_host.cpp", "kernels_dispatch.cpp", "hex_capi.cpp") else []
         if only is None or src in only or not os.path.exists(obj):
             cmds.append([hipcc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
@@ -74,19 +75,20 @@ def build_emulation(asan: bool = False, tsan: bool = False) -> str:
     runner hostemu_check (AddressSanitizer + UndefinedBehaviorSanitizer, or
     ThreadSanitizer), a plain g++ build of host code only."""
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [os.path.join(CSRC, "hostemu.cpp"), os.path.join(CSRC, "host_tables.cpp"), os.path.join(CSRC, "geometry.cpp")]
+    srcs = [os.path.join(CSRC, "hostemu.cpp"), os.path.join(CSRC, "host_tables.cpp"), os.path.join(CSRC, "geometry.cpp"),
+            os.path.join(CSRC, "hex_setup.cpp")]
     tmp = EMU + ".tmp"
-    _run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I" + CSRC, *srcs, "-o", tmp, "-lpthread"])
+    _run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I" + CSRC, "-I" + os.path.join(ROOT, "include"), *srcs, "-o", tmp, "-lpthread"])
     os.replace(tmp, EMU)
     out = EMU
     checked = os.path.join(CSRC, "hostemu_check.cpp")
     if asan:
         out = os.path.join(BUILD, "hostemu_asan")
         _run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
-              "-I" + CSRC, checked, *srcs, "-o", out, "-lpthread"])
+              "-I" + CSRC, "-I" + os.path.join(ROOT, "include"), checked, *srcs, "-o", out, "-lpthread"])
     if tsan:
         out = os.path.join(BUILD, "hostemu_tsan")
-        _run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=thread", "-I" + CSRC, checked, *srcs, "-o", out,
+        _run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=thread", "-I" + CSRC, "-I" + os.path.join(ROOT, "include"), checked, *srcs, "-o", out,
               "-lpthread"])
     return out
 

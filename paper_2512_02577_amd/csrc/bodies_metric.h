@@ -101,10 +101,26 @@ PMG_INLINE void contract_sub(int tid, const T *in, T *out, const T *base, const 
   }
 }
 
+// Global index of the cell at block position (dx, dy, dz) of a patch (or of one cell).
+struct BoxCells {  // structured n^d box, the block starting at cell c0
+  int n, c0[3];
+  PMG_HD long operator()(int dx, int dy, int dz) const {
+    return (long)(c0[0] + dx) + (long)n * ((c0[1] + dy) + (long)n * (c0[2] + dz));
+  }
+};
+struct ListCells {  // stored per patch: its cells in block order dx + 2 dy + 4 dz
+  const int32_t *id;
+  PMG_HD long operator()(int dx, int dy, int dz) const { return id[dx + 2 * dy + 4 * dz]; }
+};
+struct OneCell {
+  long c;
+  PMG_HD long operator()(int, int, int) const { return c; }
+};
+
 // Pointwise flux F = G g on NQ^DIM Gauss points held in gx/gy/gz (overwritten).  The
-// metric of point (i, j, k) lives in cell (c0 + i / nq, ...) at local point (i % nq, ...).
-template <int DIM, int NQ, int nq, int NT, typename T, typename S>
-PMG_INLINE void flux(int tid, T *gx, T *gy, T *gz, const S *G, int n, const int c0[3]) {
+// metric of point (i, j, k) lives in cell cm(i / nq, ...) at local point (i % nq, ...).
+template <int DIM, int NQ, int nq, int NT, typename T, typename S, class CM>
+PMG_INLINE void flux(int tid, T *gx, T *gy, T *gz, const S *G, const CM &cm) {
   constexpr int tot = ipow(NQ, DIM), nqd = ipow(nq, DIM), nc = DIM == 3 ? 6 : 3;
   // the metric loads of GF points per lane are issued together (one round trip per group)
   constexpr int RF = (tot + NT - 1) / NT, GF = RF < 3 ? RF : 3;
@@ -115,7 +131,7 @@ PMG_INLINE void flux(int tid, T *gx, T *gy, T *gz, const S *G, int n, const int 
       int e = tid + (k0 + k) * NT;
       e = e < tot ? e : tot - 1;
       const int i = e % NQ, j = (e / NQ) % NQ, l = DIM == 3 ? e / (NQ * NQ) : 0;
-      const long cell = (long)(c0[0] + i / nq) + (long)n * ((c0[1] + j / nq) + (long)n * (DIM == 3 ? c0[2] + l / nq : 0));
+      const long cell = cm(i / nq, j / nq, DIM == 3 ? l / nq : 0);
       const int loc = (i % nq) + nq * ((j % nq) + nq * (DIM == 3 ? l % nq : 0));
       const long gi = (cell * nqd + loc) * nc;
 #pragma unroll
@@ -162,9 +178,9 @@ struct MetricScratch {
 
 // out = base - A_patch in, with A evaluated through the Gauss points of the patch's cells.
 // PB: pattern of the input sweep (PatBpc for closure input, PatBpi for interior input).
-template <int DIM, int Q, class PB, int NT, typename T, typename S>
-PMG_INLINE void metric_patch(int tid, const T *in, T *out, const T *base, const QTabDev<T> &tb, const S *G, int n,
-                             const int c0[3], T *scr) {
+template <int DIM, int Q, class PB, int NT, typename T, typename S, class CM>
+PMG_INLINE void metric_patch(int tid, const T *in, T *out, const T *base, const QTabDev<T> &tb, const S *G,
+                             const CM &cm, T *scr) {
   constexpr int E = PB::nin, NQ = 2 * (Q + 1), nq = Q + 1, e = 2 * Q - 1;
   using SC = MetricScratch<DIM, Q>;
   using PD = PatDqp<Q>;
@@ -185,7 +201,7 @@ PMG_INLINE void metric_patch(int tid, const T *in, T *out, const T *base, const 
     PMG_SYNC();
     dcontract1<0, NQ, NQ, NQ, PD, NT, false, true>(tid, A, A, tb.Dqp);
     PMG_SYNC();
-    flux<3, NQ, nq, NT>(tid, A, B, C, G, n, c0);
+    flux<3, NQ, nq, NT>(tid, A, B, C, G, cm);
     PMG_SYNC();
     dcontract1<0, NQ, NQ, NQ, PD, NT, false, true>(tid, A, A, tb.DqpT);
     PMG_SYNC();
@@ -207,7 +223,7 @@ PMG_INLINE void metric_patch(int tid, const T *in, T *out, const T *base, const 
     PMG_SYNC();
     dcontract1<0, NQ, NQ, 1, PD, NT, false, true>(tid, A, A, tb.Dqp);
     PMG_SYNC();
-    flux<2, NQ, nq, NT>(tid, A, B, B, G, n, c0);
+    flux<2, NQ, nq, NT>(tid, A, B, B, G, cm);
     PMG_SYNC();
     dcontract1<0, NQ, NQ, 1, PD, NT, false, true>(tid, A, A, tb.DqpT);
     PMG_SYNC();
@@ -242,6 +258,9 @@ struct MetricSmoothArgs {
   const T *r_blocks;
   T *d_blocks;
   int first_patch;
+  // stored maps of a general hex mesh (null on the structured box): the patches of the
+  // color, each patch's (2p+1)^d closure nodes (-1 on the boundary) and its 2^d cells
+  const int32_t *plist, *pmap, *pcells;
 };
 
 template <int DIM, typename T, typename S, int NT, int P, class H>
@@ -299,14 +318,14 @@ struct MetricPatchBody {
     }
   }
 
-  template <int l>
-  PMG_INLINE static void vmult_residual(int tid, T *lds, const MetricSmoothArgs<T, S> &a, const int c0[3],
+  template <int l, class CM>
+  PMG_INLINE static void vmult_residual(int tid, T *lds, const MetricSmoothArgs<T, S> &a, const CM &cm,
                                         const T *d, const T *r, T *res) {
-    metric_patch<DIM, qd(l), PatBpi<qd(l)>, NT>(tid, d, res, r, a.lev[l].qt, a.lev[l].G, a.n, c0, lds + off_scr);
+    metric_patch<DIM, qd(l), PatBpi<qd(l)>, NT>(tid, d, res, r, a.lev[l].qt, a.lev[l].G, cm, lds + off_scr);
   }
 
-  template <int l>
-  PMG_INLINE static void cycle(int tid, T *lds, const MetricSmoothArgs<T, S> &a, long pidx, const int c0[3],
+  template <int l, class CM>
+  PMG_INLINE static void cycle(int tid, T *lds, const MetricSmoothArgs<T, S> &a, long pidx, const CM &cm,
                                const T *r, T *d, bool full) {
     const S *invD = a.lev[l].invD + pidx * ndl(l);
     if constexpr (l == 0) {
@@ -319,17 +338,17 @@ struct MetricPatchBody {
           tid, [&](int e) { return load_s<T>(invD, e); }, [&](int e, T x) { d[e] = x * r[e]; });
       PMG_SYNC();
       T *res = lds + off_res;
-      vmult_residual<l>(tid, lds, a, c0, d, r, res);
+      vmult_residual<l>(tid, lds, a, cm, d, r, res);
       PMG_SYNC();
       T *rc = lds + off_lr(l - 1), *dc = lds + off_ld(l - 1);
       T *t1 = lds + off_scr, *t2 = t1 + t1size;
       kron_dense<PatRestrict<q, qc>, false>(tid, res, rc, a.lev[l].TpT, t1, t2);
       PMG_SYNC();
-      cycle<l - 1>(tid, lds, a, pidx, c0, rc, dc, full);
+      cycle<l - 1>(tid, lds, a, pidx, cm, rc, dc, full);
       kron_dense<PatProlong<q, qc>, true>(tid, dc, d, a.lev[l].Tp, t1, t2);
       PMG_SYNC();
       if (full) {
-        vmult_residual<l>(tid, lds, a, c0, d, r, res);
+        vmult_residual<l>(tid, lds, a, cm, d, r, res);
         PMG_SYNC();
         lane_gather<ndq, NT, 16, T>(
             tid, [&](int e) { return load_s<T>(invD, e); }, [&](int e, T x) { d[e] += x * res[e]; });
@@ -340,19 +359,19 @@ struct MetricPatchBody {
 
   // ONE: the local solver is one half V-cycle (the default), compiled without the code of
   // the other variants
-  template <bool ONE = false>
-  PMG_INLINE static void local_solve(int tid, T *lds, const MetricSmoothArgs<T, S> &a, long pidx, const int c0[3]) {
+  template <bool ONE = false, class CM>
+  PMG_INLINE static void local_solve(int tid, T *lds, const MetricSmoothArgs<T, S> &a, long pidx, const CM &cm) {
     T *r = lds + off_r, *d = lds + off_d, *cc = lds + off_cc;
     if constexpr (ONE) {
-      cycle<L - 1>(tid, lds, a, pidx, c0, r, d, false);
+      cycle<L - 1>(tid, lds, a, pidx, cm, r, d, false);
       return;
     }
     const bool full = a.full != 0;
-    cycle<L - 1>(tid, lds, a, pidx, c0, r, d, full);
+    cycle<L - 1>(tid, lds, a, pidx, cm, r, d, full);
     for (int it = 1; it < a.n_iter; ++it) {
-      vmult_residual<L - 1>(tid, lds, a, c0, it == 1 ? d : cc, r, r);
+      vmult_residual<L - 1>(tid, lds, a, cm, it == 1 ? d : cc, r, r);
       PMG_SYNC();
-      cycle<L - 1>(tid, lds, a, pidx, c0, r, cc, full);
+      cycle<L - 1>(tid, lds, a, pidx, cm, r, cc, full);
       for (int e = tid; e < nd; e += NT) d[e] += cc[e];
       PMG_SYNC();
     }
@@ -396,12 +415,42 @@ struct MetricPatchBody {
         },
         [&](int e, T x) { ucl[e] = x; }, [&](int e) { return a.b[interior(e)]; }, [&](int e, T x) { r[e] = x; });
     PMG_SYNC();
-    metric_patch<DIM, P, PatBpc<P>, NT>(tid, ucl, r, r, a.lev[L - 1].qt, a.lev[L - 1].G, a.n, c0, lds + off_scr);
+    const BoxCells cm{a.n, {c0[0], c0[1], c0[2]}};
+    metric_patch<DIM, P, PatBpc<P>, NT>(tid, ucl, r, r, a.lev[L - 1].qt, a.lev[L - 1].G, cm, lds + off_scr);
     PMG_SYNC();
-    local_solve<ONE>(tid, lds, a, pidx, c0);
+    local_solve<ONE>(tid, lds, a, pidx, cm);
     const T *d = lds + off_d;
     lane_gather<nd, NT, 16, T>(
         tid, [&](int e) { return a.u[interior(e)]; }, [&](int e, T x) { a.u[interior(e)] = x + d[e]; });
+  }
+
+  // The same on a general hex mesh through its stored maps: the color's patch list, the
+  // patch's closure nodes (-1 on the Dirichlet boundary, gathered as zero) and its cells.
+  template <bool ONE = false>
+  PMG_INLINE static void smooth_patch_stored(int tid, int blk, T *lds, const MetricSmoothArgs<T, S> &a) {
+    const long pidx = a.plist[xcd_remap(blk, a.n_patch)];
+    const int32_t *cl = a.pmap + pidx * Nd;
+    T *ucl = lds + off_ucl, *r = lds + off_r;
+    const int ez = DIM == 3 ? 1 : 0;
+    auto interior = [&](int e) {  // closure position of interior node e
+      const int i = e % n, j = (e / n) % n, k = DIM == 3 ? e / (n * n) : 0;
+      return (i + 1) + N * ((j + 1) + N * (k + ez));
+    };
+    lane_gather2<Nd, nd, NT, 16, T>(
+        tid,
+        [&](int e) {
+          const int g = cl[e];
+          return g >= 0 ? a.u[g] : T(0);
+        },
+        [&](int e, T x) { ucl[e] = x; }, [&](int e) { return a.b[cl[interior(e)]]; }, [&](int e, T x) { r[e] = x; });
+    PMG_SYNC();
+    const ListCells cm{a.pcells + pidx * (1 << DIM)};
+    metric_patch<DIM, P, PatBpc<P>, NT>(tid, ucl, r, r, a.lev[L - 1].qt, a.lev[L - 1].G, cm, lds + off_scr);
+    PMG_SYNC();
+    local_solve<ONE>(tid, lds, a, pidx, cm);
+    const T *d = lds + off_d;
+    lane_gather<nd, NT, 16, T>(
+        tid, [&](int e) { return a.u[cl[interior(e)]]; }, [&](int e, T x) { a.u[cl[interior(e)]] = x + d[e]; });
   }
 
   PMG_INLINE static void local_only(int tid, int blk, T *lds, const MetricSmoothArgs<T, S> &a) {
@@ -413,7 +462,7 @@ struct MetricPatchBody {
     const size_t base = (size_t)blk * nd;
     lane_gather<nd, NT, 16, T>(tid, [&](int e) { return a.r_blocks[base + e]; }, [&](int e, T x) { r[e] = x; });
     PMG_SYNC();
-    local_solve(tid, lds, a, pidx, c0);
+    local_solve(tid, lds, a, pidx, BoxCells{a.n, {c0[0], c0[1], c0[2]}});
     const T *d = lds + off_d;
     for (int e = tid; e < nd; e += NT) a.d_blocks[base + e] = d[e];
   }
@@ -436,6 +485,10 @@ struct MetricApplyArgs {
   T sign;         // +1 apply, -1 residual
   const T *u;
   T *out;
+  // stored maps of a general hex mesh (null on the structured box): the cells of the
+  // color and each cell's (p+1)^d nodes; bnd marks the Dirichlet nodes
+  const int32_t *clist, *cdof;
+  const unsigned char *bnd;
 };
 
 template <int DIM, typename T, typename S, int NT, int P>
@@ -446,21 +499,41 @@ struct MetricApplyBody {
   static constexpr int w2 = DIM == 3 ? nq * nq * k : 0;
   static constexpr int size = kd + w1 + w2 + (DIM == 3 ? 4 : 3) * q3;
 
+  // STORED: the cell and its nodes come from the stored maps of a general hex mesh
+  template <bool STORED = false>
   PMG_INLINE static void run(int tid, int blk, T *lds, const MetricApplyArgs<T, S> &a) {
     const int idx = xcd_remap(blk, a.n_cells);
-    const int cx = a.first[0] + 2 * (idx % a.cnt[0]);
-    const int cy = a.first[1] + 2 * ((idx / a.cnt[0]) % a.cnt[1]);
-    const int cz = DIM == 3 ? a.first[2] + 2 * (idx / (a.cnt[0] * a.cnt[1])) : 0;
+    int cx = 0, cy = 0, cz = 0;
+    long cell = 0;
+    if constexpr (STORED) {
+      cell = a.clist[idx];
+    } else {
+      cx = a.first[0] + 2 * (idx % a.cnt[0]);
+      cy = a.first[1] + 2 * ((idx / a.cnt[0]) % a.cnt[1]);
+      cz = DIM == 3 ? a.first[2] + 2 * (idx / (a.cnt[0] * a.cnt[1])) : 0;
+      cell = cx + (long)a.n * (cy + (long)a.n * cz);
+    }
     const int m = P * a.n + 1;
+    // global index of cell node e and whether it is a Dirichlet node
+    auto node = [&](int e, bool &bnd) -> long {
+      if constexpr (STORED) {
+        const long g = a.cdof[cell * kd + e];
+        bnd = a.bnd[g] != 0;
+        return g;
+      } else {
+        const int i = e % k, j = (e / k) % k, l = DIM == 3 ? e / (k * k) : 0;
+        const int X = P * cx + i, Y = P * cy + j, Z = P * cz + l;
+        bnd = X == 0 || X == m - 1 || Y == 0 || Y == m - 1;
+        if (DIM == 3) bnd = bnd || Z == 0 || Z == m - 1;
+        return X + (long)m * (Y + (long)m * Z);
+      }
+    };
     T *ue = lds, *w1b = ue + kd, *w2b = w1b + w1, *V = w2b + w2, *gx = V + q3, *gy = gx + q3, *gz = gy + q3;
     lane_gather<kd, NT, 16, T>(
         tid,
         [&](int e) {
-          const int i = e % k, j = (e / k) % k, l = DIM == 3 ? e / (k * k) : 0;
-          const int X = P * cx + i, Y = P * cy + j, Z = P * cz + l;
-          bool bnd = X == 0 || X == m - 1 || Y == 0 || Y == m - 1;
-          if (DIM == 3) bnd = bnd || Z == 0 || Z == m - 1;
-          const T x = a.u[X + (long)m * (Y + (long)m * Z)];
+          bool bnd;
+          const T x = a.u[node(e, bnd)];
           return bnd ? T(0) : x;
         },
         [&](int e, T x) { ue[e] = x; });
@@ -468,7 +541,7 @@ struct MetricApplyBody {
     using PB = PatDense<nq, k>;
     using PD = PatDense<nq, nq>;
     using PBT = PatDense<k, nq>;
-    const int c0[3] = {cx, cy, cz};
+    const OneCell cm{cell};
     if constexpr (DIM == 3) {
       contract1<0, k, k, k, PB, NT, false>(tid, ue, w1b, a.qt.B);
       PMG_SYNC();
@@ -480,7 +553,7 @@ struct MetricApplyBody {
       contract1<1, nq, nq, nq, PD, NT, false>(tid, V, gy, a.qt.Dq);
       contract1<2, nq, nq, nq, PD, NT, false>(tid, V, gz, a.qt.Dq);
       PMG_SYNC();
-      flux<3, nq, nq, NT>(tid, gx, gy, gz, a.G, a.n, c0);
+      flux<3, nq, nq, NT>(tid, gx, gy, gz, a.G, cm);
       PMG_SYNC();
       contract1<0, nq, nq, nq, PD, NT, false>(tid, gx, V, a.qt.DqT);
       PMG_SYNC();
@@ -501,7 +574,7 @@ struct MetricApplyBody {
       contract1<0, nq, nq, 1, PD, NT, false>(tid, V, gx, a.qt.Dq);
       contract1<1, nq, nq, 1, PD, NT, false>(tid, V, gy, a.qt.Dq);
       PMG_SYNC();
-      flux<2, nq, nq, NT>(tid, gx, gy, gz, a.G, a.n, c0);
+      flux<2, nq, nq, NT>(tid, gx, gy, gz, a.G, cm);
       PMG_SYNC();
       contract1<0, nq, nq, 1, PD, NT, false>(tid, gx, V, a.qt.DqT);
       PMG_SYNC();
@@ -514,13 +587,6 @@ struct MetricApplyBody {
     PMG_SYNC();
     // out += sign * (cell result) on the cell's interior-of-mesh nodes (cells of one color
     // share no node); the loads of out are batched
-    auto node = [&](int e, bool &bnd) {
-      const int i = e % k, j = (e / k) % k, l = DIM == 3 ? e / (k * k) : 0;
-      const int X = P * cx + i, Y = P * cy + j, Z = P * cz + l;
-      bnd = X == 0 || X == m - 1 || Y == 0 || Y == m - 1;
-      if (DIM == 3) bnd = bnd || Z == 0 || Z == m - 1;
-      return X + (long)m * (Y + (long)m * Z);
-    };
     lane_gather<kd, NT, 16, T>(
         tid,
         [&](int e) {
@@ -541,6 +607,15 @@ PMG_INLINE void metric_apply_init(long g, int dim, int m, bool resid, const T *b
   const int i = (int)(g % m), j = (int)((g / m) % m), k = dim == 3 ? (int)(g / ((long)m * m)) : 1;
   const bool bnd = i == 0 || i == m - 1 || j == 0 || j == m - 1 || k == 0 || k == m - 1;
   if (bnd)
+    out[g] = resid ? b[g] - u[g] : u[g];
+  else
+    out[g] = resid ? b[g] : T(0);
+}
+
+// the same on a general hex mesh: bnd marks the Dirichlet nodes
+template <typename T>
+PMG_INLINE void hex_apply_init(long g, bool resid, const unsigned char *bnd, const T *b, const T *u, T *out) {
+  if (bnd[g])
     out[g] = resid ? b[g] - u[g] : u[g];
   else
     out[g] = resid ? b[g] : T(0);
@@ -608,4 +683,33 @@ PMG_INLINE void patch_inv_diag(long t, int q, int n, double omega, const double 
   out[t] = to_storage<S>(omega / s);
 }
 
+}  // namespace pmg
+
+namespace pmg {
+// t = patch * (2q-1)^d + e on a general hex mesh: the patch's cells come from its stored
+// list (block position dx + 2 dy + 4 dz); otherwise as patch_inv_diag.
+template <int DIM, typename S>
+PMG_INLINE void patch_inv_diag_list(long t, int q, const int32_t *pcells, double omega, const double *cdiag, S *out) {
+  const int e1 = 2 * q - 1, k = q + 1, kd = DIM == 3 ? k * k * k : k * k;
+  const long ndp = DIM == 3 ? (long)e1 * e1 * e1 : (long)e1 * e1;
+  const long p = t / ndp;
+  const int e = (int)(t % ndp);
+  const int ii[3] = {e % e1 + 1, (e / e1) % e1 + 1, DIM == 3 ? e / (e1 * e1) + 1 : 0};
+  double s = 0.0;
+  const int ncell = 1 << DIM;
+  for (int cc = 0; cc < ncell; ++cc) {
+    int loc[3] = {0, 0, 0};
+    bool in = true;
+    for (int d = 0; d < DIM; ++d) {
+      const int l = ii[d] - ((cc >> d) & 1) * q;
+      if (l < 0 || l > q) in = false;
+      loc[d] = l;
+    }
+    if (!in) continue;
+    const long cidx = pcells[p * ncell + cc];
+    const int lidx = loc[0] + k * (loc[1] + k * (DIM == 3 ? loc[2] : 0));
+    s += cdiag[cidx * kd + lidx];
+  }
+  out[t] = to_storage<S>(omega / s);
+}
 }  // namespace pmg

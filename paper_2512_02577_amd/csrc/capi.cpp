@@ -485,11 +485,7 @@ size_t noalloc_layout(pmg_problem *pr, int mg_prec, char *base, VWork<double> &w
 
 template <typename T>
 int dev_alloc(pmg_problem *pr, T **out, size_t count) {
-  void *ptr = nullptr;
-  PMG_HIP(hipMalloc(&ptr, count * sizeof(T) + 64));
-  pr->allocs.push_back(ptr);
-  *out = reinterpret_cast<T *>(ptr);
-  return PMG_OK;
+  return dev_alloc_in(pr->allocs, out, count);
 }
 
 void release(pmg_problem *pr) {
@@ -500,19 +496,21 @@ void release(pmg_problem *pr) {
   pr->dev = false;
 }
 
-// Device data of the general path: 1D Gauss-point tables per p-level, the metric of every
-// (h-level, p-level) in FP64/FP32/BF16, per-patch inverse diagonals computed on the device
-// from element diagonals, and the dense inverse of the coarsest interior operator.
-int init_general(pmg_problem *pr) {
-  const int L = pr->nplev(), nh = (int)pr->sizes.size(), dim = pr->dim;
+}  // namespace
+
+int pmg::upload_qtabs(std::vector<void *> &allocs, const std::vector<int> &degrees,
+                      std::vector<QTabDev<double>> &q64, std::vector<QTabDev<float>> &q32,
+                      std::vector<const double *> &B64, std::vector<const double *> &Dn64) {
+  const int L = (int)degrees.size();
   int rc = PMG_OK;
-  pr->qt64.assign(L, QTabDev<double>{});
-  pr->qt32.assign(L, QTabDev<float>{});
-  std::vector<const double *> B64(L), Dn64(L);
+  q64.assign(L, QTabDev<double>{});
+  q32.assign(L, QTabDev<float>{});
+  B64.assign(L, nullptr);
+  Dn64.assign(L, nullptr);
   for (int l = 0; l < L; ++l) {
-    const QTab t = make_qtab(pr->degrees[l]);
+    const QTab t = make_qtab(degrees[l]);
     const int k = t.q + 1;
-    dvec Dn((size_t)t.nq * k, 0.0);
+    dvec Dn((size_t)t.nq * k, 0.0);  // derivative of the nodal basis at the Gauss points
     for (int g = 0; g < t.nq; ++g)
       for (int a = 0; a < k; ++a) {
         double sum = 0.0;
@@ -529,7 +527,7 @@ int init_general(pmg_problem *pr) {
     }
     double *d64;
     float *d32;
-    if ((rc = dev_alloc(pr, &d64, flat.size())) || (rc = dev_alloc(pr, &d32, flat.size()))) return rc;
+    if ((rc = dev_alloc_in(allocs, &d64, flat.size())) || (rc = dev_alloc_in(allocs, &d32, flat.size()))) return rc;
     std::vector<float> flat32(flat.begin(), flat.end());
     PMG_HIP(hipMemcpy(d64, flat.data(), flat.size() * sizeof(double), hipMemcpyHostToDevice));
     PMG_HIP(hipMemcpy(d32, flat32.data(), flat32.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -538,11 +536,24 @@ int init_general(pmg_problem *pr) {
       q.Bpc = base + off[4]; q.Bpi = base + off[5]; q.BpiT = base + off[6]; q.Dqp = base + off[7];
       q.DqpT = base + off[8];
     };
-    bind(pr->qt64[l], d64);
-    bind(pr->qt32[l], d32);
+    bind(q64[l], d64);
+    bind(q32[l], d32);
     B64[l] = d64 + off[0];
     Dn64[l] = d64 + off[9];
   }
+  return PMG_OK;
+}
+
+namespace {
+
+// Device data of the general path: 1D Gauss-point tables per p-level, the metric of every
+// (h-level, p-level) in FP64/FP32/BF16, per-patch inverse diagonals computed on the device
+// from element diagonals, and the dense inverse of the coarsest interior operator.
+int init_general(pmg_problem *pr) {
+  const int L = pr->nplev(), nh = (int)pr->sizes.size(), dim = pr->dim;
+  int rc = PMG_OK;
+  std::vector<const double *> B64, Dn64;
+  if ((rc = upload_qtabs(pr->allocs, pr->degrees, pr->qt64, pr->qt32, B64, Dn64))) return rc;
   const size_t nslot = (size_t)nh * L;
   pr->G64.assign(nslot, nullptr);
   pr->G32.assign(nslot, nullptr);

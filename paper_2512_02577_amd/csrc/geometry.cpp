@@ -166,16 +166,22 @@ void gauss_points(int dim, int n, const dvec &verts, int q, dvec &out) {
 }
 
 bool metric(int dim, int n, const dvec &verts, int q, const double *a, dvec &G, int threads) {
+  const long ncell = dim == 3 ? (long)n * n * n : (long)n * n;
+  return metric_cells(
+      dim, ncell, [&](long c, double X[8][3]) { cell_corners(dim, n, verts, c, X); }, q, a, G, threads);
+}
+
+bool metric_cells(int dim, long ncell, const std::function<void(long, double[8][3])> &corners, int q,
+                  const double *a, dvec &G, int threads) {
   const int nq = q + 1, nc = metric_components(dim);
   dvec xg, wg;
   gauss_legendre(nq, xg, wg);
-  const long ncell = dim == 3 ? (long)n * n * n : (long)n * n;
   const int nqd = dim == 3 ? nq * nq * nq : nq * nq;
   G.assign((size_t)ncell * nqd * nc, 0.0);
   std::vector<char> bad(ncell, 0);
   parallel_for(ncell, threads, [&](long c) {
     double X[8][3];
-    cell_corners(dim, n, verts, c, X);
+    corners(c, X);
     for (int g = 0; g < nqd; ++g) {
       const int gx = g % nq, gy = (g / nq) % nq, gz = dim == 3 ? g / (nq * nq) : 0;
       const double xi[3] = {xg[gx], xg[gy], dim == 3 ? xg[gz] : 0.0};

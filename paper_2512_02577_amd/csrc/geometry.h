@@ -9,6 +9,7 @@
 // (the geometry and coefficient folded into one tensor, Sec. 3 stores J^{-1} and det J).
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "host_tables.h"
@@ -40,6 +41,10 @@ void gauss_points(int dim, int n, const dvec &verts, int q, dvec &out);
 // (xx, yy, zz, xy, xz, yz) in 3D and (xx, yy, xy) in 2D.  a: coefficient per Gauss point
 // (same layout, one value) or nullptr for mu = 1.  Returns false on a degenerate cell.
 bool metric(int dim, int n, const dvec &verts, int q, const double *a, dvec &G, int threads = 8);
+// The same for a list of ncell cells whose corners (lexicographic, x fastest) come from
+// corners(c, X); G and a are laid out per listed cell.
+bool metric_cells(int dim, long ncell, const std::function<void(long, double[8][3])> &corners, int q,
+                  const double *a, dvec &G, int threads = 8);
 
 // Dense interior block of the degree-p operator on a mesh of n cells per direction,
 // assembled from element matrices built with the metric G (degree p).  Interior nodes in

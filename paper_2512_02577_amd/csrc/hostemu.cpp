@@ -25,6 +25,7 @@
 #include "constants.h"
 #include "dispatch.h"
 #include "geometry.h"
+#include "hex_setup.h"
 #include "host_tables.h"
 #include "tab_layout.h"
 
@@ -347,6 +348,95 @@ void emu_inv_diag(int n, int q, double omega, const dvec &G, dvec &invD) {
   for (long tt = 0; tt < np * nd; ++tt) patch_inv_diag<DIM, double>(tt, q, n, omega, cd.data(), invD.data());
 }
 
+// General hex meshes: the stored-map bodies over the colors of a HexHost
+template <int DIM>
+struct EmuHexSmooth {
+  template <int P, class H>
+  struct F {
+    template <int NT, bool ONE>
+    static int go(const MetricSmoothArgs<double, double> &base, const HexHost &h, int color_dir) {
+      using B = MetricPatchBody<DIM, double, double, NT, P, H>;
+      std::vector<double> lds(B::arena(base.n_iter));
+      const int ncol = (int)h.pfirst.size() - 1;
+      for (int ci = 0; ci < ncol; ++ci) {
+        const int col = color_dir > 0 ? ci : ncol - 1 - ci;
+        MetricSmoothArgs<double, double> a = base;
+        a.plist = h.plist.data() + h.pfirst[col];
+        a.n_patch = h.pfirst[col + 1] - h.pfirst[col];
+        launch<NT>(a.n_patch, lds,
+                   [&](int tid, int blk, double *ar) { B::template smooth_patch_stored<ONE>(tid, blk, ar, a); });
+      }
+      return 0;
+    }
+    static int run(const MetricSmoothArgs<double, double> &base, const HexHost &h, int color_dir, int lanes, int one) {
+      const bool o = one != 0;
+      if (o && (base.full || base.n_iter != 1)) return -3;
+      constexpr int W = metric_patch_threads(P, sizeof(double));
+      if (lanes == 0) return o ? go<1, true>(base, h, color_dir) : go<1, false>(base, h, color_dir);
+      if (lanes == 1) return o ? go<W, true>(base, h, color_dir) : go<W, false>(base, h, color_dir);
+      return -1;
+    }
+  };
+};
+
+template <int DIM>
+struct EmuHexApply {
+  template <int P>
+  struct F {
+    template <int NT>
+    static int go(const MetricApplyArgs<double, double> &base, const HexHost &h) {
+      using B = MetricApplyBody<DIM, double, double, NT, P>;
+      std::vector<double> lds(B::size);
+      const int ncol = (int)h.cfirst.size() - 1;
+      for (int col = 0; col < ncol; ++col) {
+        MetricApplyArgs<double, double> a = base;
+        a.clist = h.clist.data() + h.cfirst[col];
+        a.n_cells = h.cfirst[col + 1] - h.cfirst[col];
+        launch<NT>(a.n_cells, lds, [&](int tid, int blk, double *ar) { B::template run<true>(tid, blk, ar, a); });
+      }
+      return 0;
+    }
+    static int run(const MetricApplyArgs<double, double> &base, const HexHost &h, int lanes) {
+      if (lanes == 0) return go<1>(base, h);
+      if (lanes == 1) return go<metric_apply_threads(P)>(base, h);
+      return -1;
+    }
+  };
+};
+
+// metric of degree q on the cells of a HexHost (corners in the common frame)
+bool hex_metric(const HexHost &h, int q, dvec &G) {
+  const int dim = h.dim, ncn = 1 << dim;
+  return metric_cells(
+      dim, h.n_cells,
+      [&](long c, double X[8][3]) {
+        for (int j = 0; j < ncn; ++j)
+          for (int a = 0; a < dim; ++a) X[j][a] = h.xyz[(size_t)h.cverts[(size_t)c * ncn + j] * dim + a];
+      },
+      q, nullptr, G);
+}
+
+// per-patch inverse diagonals of one p-level on a HexHost
+template <int DIM>
+void emu_hex_inv_diag(const HexHost &h, int q, double omega, const dvec &G, dvec &invD) {
+  const QTab t = make_qtab(q);
+  const int k = q + 1;
+  dvec Dn((size_t)t.nq * k, 0.0);
+  for (int g = 0; g < t.nq; ++g)
+    for (int a = 0; a < k; ++a) {
+      double s = 0.0;
+      for (int hh = 0; hh < t.nq; ++hh) s += t.Dq[(size_t)g * t.nq + hh] * t.B[(size_t)hh * k + a];
+      Dn[(size_t)g * k + a] = s;
+    }
+  const long kd = DIM == 3 ? k * k * k : k * k;
+  dvec cd((size_t)(h.n_cells * kd));
+  for (long tt = 0; tt < h.n_cells * kd; ++tt) cell_diag<DIM, double>(tt, q, t.B.data(), Dn.data(), G.data(), cd.data());
+  const long e1 = 2 * q - 1, nd = DIM == 3 ? e1 * e1 * e1 : e1 * e1, np = (long)h.pvert.size();
+  invD.assign((size_t)(np * nd), 0.0);
+  for (long tt = 0; tt < np * nd; ++tt)
+    patch_inv_diag_list<DIM, double>(tt, q, h.pcells.data(), omega, cd.data(), invD.data());
+}
+
 // Cartesian patch-solver arguments: local 0 half V-cycle, 1 full V-cycle, 2 exact solve;
 // reinf: Cartesian-reinforced p-level preconditioner (damping omega) instead of Jacobi
 void set_local(SmoothArgs<double> &a, const HostTabs &h, int local, int reinf) {
@@ -422,6 +512,71 @@ int pmgemu_metric_smooth(int dim, int n, int p, const int *deg, int L, const dou
   if (code < 0) return -2;
   if (dim == 3) return dispatch_hierarchy<EmuMetricSmooth<3>::F>(p, code, a, n, color_dir, nb > 0, nb, lanes, one);
   return dispatch_hierarchy<EmuMetricSmooth<2>::F>(p, code, a, n, color_dir, nb > 0, nb, lanes, one);
+}
+
+// General hex mesh (hex_build's arrays): the stored-map apply (resid: out = b - A u).
+int pmgemu_hex_apply(int dim, int p, long nv, const double *xyz, long nc, const int32_t *cv, long ndof,
+                     const int32_t *cd, int resid, const double *u, const double *b, double *out, int lanes) {
+  HexHost h;
+  std::string err;
+  if (int rc = hex_build(dim, p, nv, xyz, nc, cv, ndof, cd, h, err)) return rc;
+  dvec G;
+  if (!hex_metric(h, p, G)) return -1;
+  HostQ hq;
+  hq.t = make_qtab(p);
+  hq.bind();
+  for (long g = 0; g < ndof; ++g) hex_apply_init<double>(g, resid != 0, h.bnd.data(), b, u, out);
+  MetricApplyArgs<double, double> a{};
+  a.qt = hq.d;
+  a.G = G.data();
+  a.sign = resid ? -1.0 : 1.0;
+  a.u = u;
+  a.out = out;
+  a.cdof = h.cdofs.data();
+  a.bnd = h.bnd.data();
+  if (dim == 3) return dispatch_degree<EmuHexApply<3>::F>(p, a, h, lanes);
+  return dispatch_degree<EmuHexApply<2>::F>(p, a, h, lanes);
+}
+
+// General hex mesh: one smoother application over the DSATUR colors (paper p-hierarchy;
+// omega: one damping per p-level, coarsest first).
+int pmgemu_hex_smooth(int dim, int p, const double *omega, long nv, const double *xyz, long nc, const int32_t *cv,
+                      long ndof, const int32_t *cd, int full, int n_iter, int color_dir, double *u, const double *b,
+                      int lanes, int one) {
+  HexHost h;
+  std::string err;
+  if (int rc = hex_build(dim, p, nv, xyz, nc, cv, ndof, cd, h, err)) return rc;
+  std::vector<int> deg;
+  for (int x = 1; x < p; x = 2 * x + 1) deg.push_back(x);
+  deg.push_back(p);
+  const int L = (int)deg.size();
+  Tables tab;
+  build_tables(dim, p, deg, dvec(omega, omega + L), 2, tab);
+  std::vector<HostQ> hq(L);
+  std::vector<dvec> G(L), invD(L);
+  MetricSmoothArgs<double, double> a{};
+  for (int l = 0; l < L; ++l) {
+    hq[l].t = make_qtab(deg[l]);
+    hq[l].bind();
+    if (!hex_metric(h, deg[l], G[l])) return -1;
+    if (dim == 3)
+      emu_hex_inv_diag<3>(h, deg[l], l == 0 ? 1.0 : omega[l], G[l], invD[l]);
+    else
+      emu_hex_inv_diag<2>(h, deg[l], l == 0 ? 1.0 : omega[l], G[l], invD[l]);
+    a.lev[l].qt = hq[l].d;
+    a.lev[l].G = G[l].data();
+    a.lev[l].invD = invD[l].data();
+    a.lev[l].Tp = tab.lev[l].Tp.empty() ? nullptr : tab.lev[l].Tp.data();
+    a.lev[l].TpT = tab.lev[l].TpT.empty() ? nullptr : tab.lev[l].TpT.data();
+  }
+  a.full = full;
+  a.n_iter = n_iter;
+  a.u = u;
+  a.b = b;
+  a.pmap = h.pmap.data();
+  a.pcells = h.pcells.data();
+  if (dim == 3) return dispatch_hierarchy<EmuHexSmooth<3>::F>(p, 0, a, h, color_dir, lanes, one);
+  return dispatch_hierarchy<EmuHexSmooth<2>::F>(p, 0, a, h, color_dir, lanes, one);
 }
 
 // One smoother application (all colors) on a single Cartesian level of n^dim cells.

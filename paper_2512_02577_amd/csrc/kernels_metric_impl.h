@@ -76,6 +76,47 @@ __global__ __launch_bounds__(256) void k_minit(int dim, int m, int resid, const 
   if (g < n) metric_apply_init<T>(g, dim, m, resid != 0, b, u, out);
 }
 
+// general hex meshes: the same bodies through the stored maps
+template <int DIM, typename T, int P, class H, bool ONE>
+__global__ __launch_bounds__(metric_patch_threads(P, sizeof(T))) void k_hsmooth(MetricSmoothArgs<T, T> a) {
+  using B = MetricPatchBody<DIM, T, T, metric_patch_threads(P, sizeof(T)), P, H>;
+  B::template smooth_patch_stored<ONE>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+}
+
+template <int DIM, typename T, int P, class H>
+__global__ __launch_bounds__(metric_patch_threads(P, sizeof(T))) void k_hsmooth_g(MetricSmoothArgs<T, T> a,
+                                                                            void *garena) {
+  using B = MetricPatchBody<DIM, T, T, metric_patch_threads(P, sizeof(T)), P, H>;
+  T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
+  for (int blk = blockIdx.x; blk < a.n_patch; blk += gridDim.x) {
+    B::smooth_patch_stored(threadIdx.x, blk, ar, a);
+    __syncthreads();
+  }
+}
+
+template <int DIM, typename T, int P>
+__global__ __launch_bounds__(metric_apply_threads(P)) void k_happly(MetricApplyArgs<T, T> a) {
+  using B = MetricApplyBody<DIM, T, T, metric_apply_threads(P), P>;
+  B::template run<true>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+}
+
+template <int DIM, typename T, int P>
+__global__ __launch_bounds__(metric_apply_threads(P)) void k_happly_g(MetricApplyArgs<T, T> a, void *garena) {
+  using B = MetricApplyBody<DIM, T, T, metric_apply_threads(P), P>;
+  T *ar = reinterpret_cast<T *>(garena) + (size_t)blockIdx.x * B::size;
+  for (int blk = blockIdx.x; blk < a.n_cells; blk += gridDim.x) {
+    B::template run<true>(threadIdx.x, blk, ar, a);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_hinit(int resid, const unsigned char *bnd, const T *b, const T *u, T *out,
+                                               long n) {
+  const long g = (long)blockIdx.x * 256 + threadIdx.x;
+  if (g < n) hex_apply_init<T>(g, resid != 0, bnd, b, u, out);
+}
+
 template <typename KL, typename KG, typename... Args>
 int launch_arena(KL klds, KG kglob, int nblk, int threads, size_t bytes, const Arena &ar, hipStream_t s,
                  Args... args) {
@@ -161,7 +202,63 @@ struct ApplyBytesF {
   };
 };
 
+template <int DIM, typename T>
+struct HSmoothF {
+  template <int P, class H>
+  struct F {
+    static int run(const MetricSmoothArgs<T, T> &a, const Arena &ar, hipStream_t s) {
+      using B = MetricPatchBody<DIM, T, T, metric_patch_threads(P, sizeof(T)), P, H>;
+      const size_t bytes = B::arena(a.n_iter) * sizeof(T);
+      if (a.full == 0 && a.n_iter == 1)
+        return launch_arena(k_hsmooth<DIM, T, P, H, true>, k_hsmooth_g<DIM, T, P, H>, a.n_patch,
+                            metric_patch_threads(P, sizeof(T)), bytes, ar, s, a);
+      return launch_arena(k_hsmooth<DIM, T, P, H, false>, k_hsmooth_g<DIM, T, P, H>, a.n_patch,
+                          metric_patch_threads(P, sizeof(T)), bytes, ar, s, a);
+    }
+  };
+};
+
+template <int DIM, typename T>
+struct HApplyF {
+  template <int P>
+  struct F {
+    static int run(const MetricApplyArgs<T, T> &a, const Arena &ar, hipStream_t s) {
+      using B = MetricApplyBody<DIM, T, T, metric_apply_threads(P), P>;
+      return launch_arena(k_happly<DIM, T, P>, k_happly_g<DIM, T, P>, a.n_cells, metric_apply_threads(P),
+                          B::size * sizeof(T), ar, s, a);
+    }
+  };
+};
+
 }  // namespace mdetail
+
+template <int DIM, typename T>
+size_t HexLaunchers<DIM, T>::patch_bytes(int p) {
+  return MetricLaunchers<DIM, T, T>::patch_bytes(p);
+}
+
+template <int DIM, typename T>
+size_t HexLaunchers<DIM, T>::apply_bytes(int p) {
+  return MetricLaunchers<DIM, T, T>::apply_bytes(p);
+}
+
+template <int DIM, typename T>
+int HexLaunchers<DIM, T>::smooth(int p, const MetricSmoothArgs<T, T> &a, const Arena &ar, hipStream_t s) {
+  return dispatch_hierarchy<mdetail::HSmoothF<DIM, T>::template F>(p, 0, a, ar, s);
+}
+
+template <int DIM, typename T>
+int HexLaunchers<DIM, T>::apply(int p, const MetricApplyArgs<T, T> &a, const Arena &ar, hipStream_t s) {
+  return dispatch_degree<mdetail::HApplyF<DIM, T>::template F>(p, a, ar, s);
+}
+
+template <int DIM, typename T>
+int HexLaunchers<DIM, T>::apply_init(long n, bool resid, const unsigned char *bnd, const T *b, const T *u, T *out,
+                                     hipStream_t s) {
+  hipLaunchKernelGGL((mdetail::k_hinit<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int)resid, bnd, b, u,
+                     out, n);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
 
 template <int DIM, typename T, typename S>
 size_t MetricLaunchers<DIM, T, S>::patch_bytes(int p) {

@@ -33,6 +33,21 @@ int fail(int code, const char *fmt, ...);
                   hipGetErrorString(e_));                                                     \
   } while (0)
 
+// hipMalloc of count elements (plus slack), recorded in allocs for release.
+template <typename T>
+int dev_alloc_in(std::vector<void *> &allocs, T **out, size_t count) {
+  void *ptr = nullptr;
+  PMG_HIP(hipMalloc(&ptr, count * sizeof(T) + 64));
+  allocs.push_back(ptr);
+  *out = reinterpret_cast<T *>(ptr);
+  return 0;
+}
+
+// 1D Gauss-point tables of the metric path for every degree, in FP64 and FP32 on the
+// device; B64/Dn64: the FP64 basis values and nodal-basis derivatives at the Gauss points.
+int upload_qtabs(std::vector<void *> &allocs, const std::vector<int> &degrees, std::vector<QTabDev<double>> &q64,
+                 std::vector<QTabDev<float>> &q32, std::vector<const double *> &B64, std::vector<const double *> &Dn64);
+
 template <typename T>
 struct PrecData {
   DevTabs<T> tabs{};

@@ -22,6 +22,13 @@ __global__ __launch_bounds__(256) void k_patch_invdiag(int q, int n, double omeg
   if (t < total) patch_inv_diag<DIM, S>(t, q, n, omega, cdiag, out);
 }
 
+template <int DIM, typename S>
+__global__ __launch_bounds__(256) void k_patch_invdiag_list(int q, double omega, long total, const int32_t *pcells,
+                                                            const double *cdiag, S *out) {
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t < total) patch_inv_diag_list<DIM, S>(t, q, pcells, omega, cdiag, out);
+}
+
 __global__ __launch_bounds__(256) void k_identity(double *A, int m) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i < m) A[i * m + i] = 1.0;
@@ -95,6 +102,20 @@ int launch_patch_invdiag(int dim, int q, int n, double omega, const double *cdia
   return ok();
 }
 
+template <typename S>
+int launch_patch_invdiag_list(int dim, int q, long np, const int32_t *pcells, double omega, const double *cdiag,
+                              S *invD, hipStream_t s) {
+  const long e1 = 2 * q - 1;
+  const long total = dim == 3 ? np * e1 * e1 * e1 : np * e1 * e1;
+  if (total == 0) return 0;
+  const unsigned grid = (unsigned)((total + 255) / 256);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_patch_invdiag_list<3, S>), dim3(grid), dim3(256), 0, s, q, omega, total, pcells, cdiag, invD);
+  else
+    hipLaunchKernelGGL((k_patch_invdiag_list<2, S>), dim3(grid), dim3(256), 0, s, q, omega, total, pcells, cdiag, invD);
+  return ok();
+}
+
 int launch_set_identity(double *A, int m, hipStream_t s) {
   hipLaunchKernelGGL(k_identity, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A, m);
   return ok();
@@ -119,6 +140,10 @@ int launch_coarse_dense(int dim, int mi, int mt, const double *Ainv, const T *r,
 template int launch_patch_invdiag<double>(int, int, int, double, const double *, double *, hipStream_t);
 template int launch_patch_invdiag<float>(int, int, int, double, const double *, float *, hipStream_t);
 template int launch_patch_invdiag<bf16>(int, int, int, double, const double *, bf16 *, hipStream_t);
+template int launch_patch_invdiag_list<double>(int, int, long, const int32_t *, double, const double *, double *,
+                                               hipStream_t);
+template int launch_patch_invdiag_list<float>(int, int, long, const int32_t *, double, const double *, float *,
+                                              hipStream_t);
 template int launch_convert<float>(const double *, float *, long, hipStream_t);
 template int launch_convert<bf16>(const double *, bf16 *, long, hipStream_t);
 template int launch_coarse_dense<double>(int, int, int, const double *, const double *, double *, double *,

@@ -86,6 +86,16 @@ def lib() -> ctypes.CDLL:
             "pmg_batch_vcycle": (_ip, [_vp, _ip, P(_vp), P(_vp), _vp]),
             "pmg_batch_solve": (_ip, [_vp, _ip, P(_vp), P(_vp), P(SolveInfo), _vp]),
             "pmg_destroy_batch": (None, [_vp]),
+            "pmg_setup_hex": (_ip, [_ip, _ip, ctypes.c_int64, P(_dp), ctypes.c_int64, P(ctypes.c_int32),
+                                    ctypes.c_int64, P(ctypes.c_int32), P(Config), P(_vp)]),
+            "pmg_hex_sizes": (_ip, [_vp, P(ctypes.c_int64), P(_ip), P(_ip), P(_ip), P(ctypes.c_int32), P(_dp)]),
+            "pmg_hex_export": (_ip, [_vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32),
+                                     P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_uint8)]),
+            "pmg_hex_device_init": (_ip, [_vp]),
+            "pmg_hex_apply": (_ip, [_vp, _ip, _vp, _vp, _vp]),
+            "pmg_hex_residual": (_ip, [_vp, _ip, _vp, _vp, _vp, _vp]),
+            "pmg_hex_smooth": (_ip, [_vp, _ip, _ip, _vp, _vp, _vp]),
+            "pmg_hex_destroy": (None, [_vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -400,3 +410,72 @@ def batch_solve(bt: Batch, b, x, mg_prec: int = FP32, raise_on_failure: bool = T
     if rc != OK and raise_on_failure:
         raise PmgError(rc, last_error())
     return list(infos)
+
+
+# ---------------------------------------------------------------------------------------
+# General hex meshes with stored maps
+# ---------------------------------------------------------------------------------------
+class HexProblem:
+    """Handle of a pmg_hex (setup_hex) with its sizes."""
+
+    def __init__(self, handle: ctypes.c_void_p, dim: int, degree: int, n_cells: int, n_dofs: int):
+        self.handle = handle
+        self.dim, self.p, self.n_cells, self.n_dofs = dim, degree, n_cells, n_dofs
+        npat, npc, ncc, npl = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().pmg_hex_sizes(handle, ctypes.byref(npat), ctypes.byref(npc), ctypes.byref(ncc),
+                                   ctypes.byref(npl), None, None))
+        self.n_patches, self.n_patch_colors, self.n_cell_colors = npat.value, npc.value, ncc.value
+        deg = (ctypes.c_int32 * npl.value)()
+        om = (ctypes.c_double * npl.value)()
+        _check(lib().pmg_hex_sizes(handle, None, None, None, None, deg, om))
+        self.degrees, self.omega = list(deg), list(om)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.pmg_hex_destroy(self.handle)
+            self.handle = None
+
+
+def setup_hex(dim: int, degree: int, vertices, cell_vertices, cell_dofs, n_dofs: int,
+              config: Config | None = None) -> HexProblem:
+    P = ctypes.POINTER
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    cv = np.ascontiguousarray(cell_vertices, dtype=np.int32)
+    cd = np.ascontiguousarray(cell_dofs, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(lib().pmg_setup_hex(dim, degree, len(v), v.ctypes.data_as(P(ctypes.c_double)), len(cv),
+                               cv.ctypes.data_as(P(ctypes.c_int32)), int(n_dofs), cd.ctypes.data_as(P(ctypes.c_int32)),
+                               ctypes.byref(config) if config is not None else None, ctypes.byref(h)))
+    return HexProblem(h, dim, degree, len(cv), int(n_dofs))
+
+
+def hex_export(hp: HexProblem) -> dict:
+    P = ctypes.POINTER
+    ncn, N = 2 ** hp.dim, (2 * hp.p + 1) ** hp.dim
+    out = {"patch_vertex": np.empty(hp.n_patches, np.int32), "patch_color": np.empty(hp.n_patches, np.int32),
+           "patch_cells": np.empty((hp.n_patches, ncn), np.int32),
+           "patch_closure": np.empty((hp.n_patches, N), np.int32), "cell_color": np.empty(hp.n_cells, np.int32),
+           "boundary": np.empty(hp.n_dofs, np.uint8)}
+    i32 = lambda a: a.ctypes.data_as(P(ctypes.c_int32))  # noqa: E731
+    _check(lib().pmg_hex_export(hp.handle, i32(out["patch_vertex"]), i32(out["patch_color"]),
+                                i32(out["patch_cells"]), i32(out["patch_closure"]), i32(out["cell_color"]),
+                                out["boundary"].ctypes.data_as(P(ctypes.c_uint8))))
+    return out
+
+
+def hex_device_init(hp: HexProblem) -> None:
+    _check(lib().pmg_hex_device_init(hp.handle))
+
+
+def hex_apply(hp: HexProblem, u, v) -> None:
+    _check(lib().pmg_hex_apply(hp.handle, _prec_of(u), _ptr(u, hp.n_dofs), _ptr(v, hp.n_dofs, u.dtype), _stream()))
+
+
+def hex_residual(hp: HexProblem, b, u, r) -> None:
+    _check(lib().pmg_hex_residual(hp.handle, _prec_of(u), _ptr(b, hp.n_dofs, u.dtype), _ptr(u, hp.n_dofs),
+                                  _ptr(r, hp.n_dofs, u.dtype), _stream()))
+
+
+def hex_smooth(hp: HexProblem, u, b, color_dir: int = 1) -> None:
+    _check(lib().pmg_hex_smooth(hp.handle, _prec_of(u), color_dir, _ptr(u, hp.n_dofs), _ptr(b, hp.n_dofs, u.dtype),
+                                _stream()))

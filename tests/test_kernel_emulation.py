@@ -297,3 +297,49 @@ def test_general_smoother_and_local_solve(emu, dim, n, p, jit, use_coef):
     for j in range(nb):
         ref = ls.local_solve(j, r[j * nd:(j + 1) * nd])
         assert abs(d[j * nd:(j + 1) * nd] - ref).max() <= 1e-12 * abs(ref).max()
+
+
+# ---- general hex meshes: the stored-map bodies against the hex-mesh oracle ----
+I32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def _hex_args(h):
+    v = np.ascontiguousarray(h["vertices"], dtype=np.float64)
+    cv = np.ascontiguousarray(h["cell_vertices"], dtype=np.int32)
+    cdofs = np.ascontiguousarray(h["cell_dofs"], dtype=np.int32)
+    return v, cv, cdofs
+
+
+@pytest.mark.parametrize("lanes", [0, 1])
+@pytest.mark.parametrize("dim,n,p,shape", [(2, 6, 3, "L"), (2, 8, 2, "hole"), (2, 4, 7, "L"), (3, 4, 2, "L"),
+                                           (3, 4, 3, "box"), (3, 4, 4, "L"), (3, 2, 6, "box")])
+def test_hex_apply_and_smoother(emu, dim, n, p, shape, lanes):
+    from oracle.hexmesh import HexLevelSmoother, HexMesh
+    from paper_2512_02577_amd.inputs import hex_mesh
+
+    emu.pmgemu_hex_apply.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, DP, ctypes.c_long, I32, ctypes.c_long,
+                                     I32, ctypes.c_int, DP, DP, DP, ctypes.c_int]
+    emu.pmgemu_hex_smooth.argtypes = [ctypes.c_int, ctypes.c_int, DP, ctypes.c_long, DP, ctypes.c_long, I32,
+                                      ctypes.c_long, I32, ctypes.c_int, ctypes.c_int, ctypes.c_int, DP, DP,
+                                      ctypes.c_int, ctypes.c_int]
+    h = hex_mesh(dim, n, p, 3, shape=shape, distortion=0.3)
+    v, cv, cdofs = _hex_args(h)
+    nd = h["n_dofs"]
+    hm = HexMesh(dim, v, cv, p, cdofs, nd)
+    rng = np.random.default_rng(2)
+    u, b = rng.uniform(-1, 1, nd), rng.uniform(-1, 1, nd)
+    ref = b - hm.stiffness() @ u
+    out = np.zeros(nd)
+    assert emu.pmgemu_hex_apply(dim, p, len(v), P(v), len(cv), cv.ctypes.data_as(I32), nd,
+                                cdofs.ctypes.data_as(I32), 1, P(u), P(b), P(out), lanes) == 0
+    assert abs(out - ref).max() <= 1e-13 * abs(ref).max()
+    if p == 8:
+        return  # the oracle's degree-8 patch smoother is minutes of CPU time
+    hs = HexLevelSmoother(hm, p_hierarchy(p))
+    om = np.ascontiguousarray(hs.omega, dtype=np.float64)
+    for direction, one in ((1, 1), (-1, 0)):
+        ue = u.copy()
+        assert emu.pmgemu_hex_smooth(dim, p, P(om), len(v), P(v), len(cv), cv.ctypes.data_as(I32), nd,
+                                     cdofs.ctypes.data_as(I32), 0, 1, direction, P(ue), P(b), lanes, one) == 0
+        uo = hs.smooth(u, b, descending=direction < 0)
+        assert abs(ue - uo).max() <= 1e-13 * abs(uo).max()
