@@ -303,6 +303,66 @@ def bench_general(torch, pmg, steps):
     return rec
 
 
+def bench_hex(torch, pmg, perfmodel, np, reps):
+    """General hex mesh with stored maps: a 3D L-shaped domain of 64^3 lattice cells minus a
+    quadrant (196,608 hexes, renumbered, rotated and reflected, vertices jittered by 0.3 h,
+    nodes numbered with locality as a DoF handler would), Q4; the stored-map apply and one smoother application (DSATUR colors) in FP64 and FP32,
+    beside the same kernels with computed indices on the 64^3 distorted box."""
+    from paper_2512_02577_amd.inputs import hex_mesh, jittered_vertices
+
+    log("bench: general hex mesh 3D L 64^3 Q4 (mesh and setup)")
+    t0 = time.perf_counter()
+    h = hex_mesh(3, 64, 4, 50, shape="L", distortion=0.3, renumber_nodes=False)
+    t_mesh = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hp = pmg.setup_hex(3, 4, h["vertices"], h["cell_vertices"], h["cell_dofs"], h["n_dofs"])
+    t_host = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pmg.hex_device_init(hp)
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    nd = h["n_dofs"]
+    rng = np.random.default_rng(51)
+    rec = {"workload": "3D Poisson on an L-shaped general hex mesh (64^3 lattice minus a quadrant, cells and vertices "
+                       "renumbered at random, cells rotated and reflected, nodes in lattice order, vertices jittered "
+                       "0.3 h), Q4, stored maps, DSATUR colors",
+           "n_cells": hp.n_cells, "n_dofs": nd, "n_patches": hp.n_patches, "patch_colors": hp.n_patch_colors,
+           "cell_colors": hp.n_cell_colors, "mesh_s": t_mesh, "host_setup_s": t_host, "device_init_s": t_dev,
+           "ms": {}, "dof_per_s": {}, "frac_hbm": {}}
+    bytes_sm = perfmodel.hex_smooth_bytes(3, 4, hp.degrees, hp.n_patches)
+    bytes_ap = perfmodel.hex_apply_bytes(3, 4, hp.n_cells, nd)
+    rec["bytes_per_application"] = {"smooth_fp64": bytes_sm, "apply_fp64": bytes_ap}
+    for dt, tag in ((torch.float64, "fp64"), (torch.float32, "fp32")):
+        u = torch.as_tensor(rng.uniform(-1, 1, nd), dtype=dt, device="cuda:0")
+        b = torch.as_tensor(rng.uniform(-1, 1, nd), dtype=dt, device="cuda:0")
+        v = torch.empty_like(u)
+        ms_ap = time_events(lambda: pmg.hex_apply(hp, u, v), reps, torch)
+        ms_sm = time_events(lambda: pmg.hex_smooth(hp, u, b, 1), max(2, reps // 4), torch)
+        rec["ms"]["apply_" + tag], rec["ms"]["smooth_" + tag] = ms_ap, ms_sm
+        rec["dof_per_s"]["apply_" + tag], rec["dof_per_s"]["smooth_" + tag] = nd / ms_ap * 1e3, nd / ms_sm * 1e3
+        if tag == "fp64":
+            rec["frac_hbm"]["apply_fp64"] = bytes_ap / (ms_ap * 1e-3) / 1e9 / HBM_PEAK_GBS
+            rec["frac_hbm"]["smooth_fp64"] = bytes_sm / (ms_sm * 1e-3) / 1e9 / HBM_PEAK_GBS
+        del u, b, v
+    del hp, h
+    torch.cuda.empty_cache()
+    log("bench: the same kernels with computed indices on the 64^3 distorted box")
+    pr = pmg.make_problem(3, 64, 4, vertices=jittered_vertices(3, 64, 0.3, 52))
+    N = pr.n_nodes[-1]
+    box = {"n_dofs": N, "ms": {}, "dof_per_s": {}}
+    u = torch.as_tensor(rng.uniform(-1, 1, N), dtype=torch.float64, device="cuda:0")
+    b = torch.as_tensor(rng.uniform(-1, 1, N), dtype=torch.float64, device="cuda:0")
+    v = torch.empty_like(u)
+    box["ms"]["apply_fp64"] = time_events(lambda: pmg.apply_operator(pr, pr.finest, u, v), reps, torch)
+    box["ms"]["smooth_fp64"] = time_events(lambda: pmg.smooth(pr, pr.finest, u, b), max(2, reps // 4), torch)
+    for k, ms in box["ms"].items():
+        box["dof_per_s"][k] = N / ms * 1e3
+    rec["distorted_box_computed_indices"] = box
+    del pr, u, b, v
+    torch.cuda.empty_cache()
+    return rec
+
+
 # Table 3's local solver strategies (Sec. 4.3), timed per patch in FP64
 LOCAL_SOLVERS = [("half V-cycle (Jacobi)", 0, 0, False, "jacobi"), ("V-cycle (Jacobi)", 1, 0, True, "jacobi"),
                  ("half V-cycle (Cartesian-reinforced)", 0, 1, False, "reinforced"),
@@ -462,6 +522,37 @@ def counters_mode(torch, pmg, np):
     return 0
 
 
+def hex_counters_mode(torch, pmg, np):
+    """Short runs of the general hex-mesh kernels for rocprofv3 passes: the 1 GiB device
+    copy (calibration), then on the 3D L of 64^3 lattice cells Q4 (as in bench_hex) one FP64
+    smoother application (one launch per DSATUR color) and three FP64 applies."""
+    from paper_2512_02577_amd.inputs import hex_mesh
+
+    dev = "cuda:0"
+    x = torch.empty(2 ** 27, dtype=torch.float64, device=dev).uniform_(-1, 1)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    torch.cuda.empty_cache()
+    log("bench: hex counter runs (3D L 64^3 Q4)")
+    h = hex_mesh(3, 64, 4, 50, shape="L", distortion=0.3, renumber_nodes=False)
+    hp = pmg.setup_hex(3, 4, h["vertices"], h["cell_vertices"], h["cell_dofs"], h["n_dofs"])
+    pmg.hex_device_init(hp)
+    nd = h["n_dofs"]
+    u = torch.as_tensor(np.random.default_rng(3).uniform(-1, 1, nd), dtype=torch.float64, device=dev)
+    b = torch.as_tensor(np.random.default_rng(4).uniform(-1, 1, nd), dtype=torch.float64, device=dev)
+    v = torch.empty_like(u)
+    pmg.hex_smooth(hp, u, b, 1)
+    for _ in range(3):
+        pmg.hex_apply(hp, u, v)
+    torch.cuda.synchronize()
+    print(json.dumps({"hex_counters": "done", "patch_colors": hp.n_patch_colors, "cell_colors": hp.n_cell_colors}),
+          flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -471,6 +562,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="leave out the 16-problem batch measurement")
     ap.add_argument("--no-sweep", action="store_true", help="leave out the degree sweep and the 128^3 rates")
+    ap.add_argument("--no-hex", action="store_true", help="leave out the general hex-mesh measurement")
+    ap.add_argument("--hex-only", action="store_true", help="only the general hex-mesh measurement")
+    ap.add_argument("--hex-counters", action="store_true", help="short hex-mesh kernel runs for rocprofv3 passes")
     ap.add_argument("--extras", action="store_true", help="also the 48^3 Q6 perturbed-mesh problem")
     ap.add_argument("--counters", action="store_true", help="short kernel runs for rocprofv3 counter passes")
     ap.add_argument("--table1", action="store_true", help="only the Table 1 iteration-count grid (minutes)")
@@ -491,8 +585,14 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         return counters_mode(torch, pmg, np)
+    if args.hex_counters:
+        return hex_counters_mode(torch, pmg, np)
     if args.table1:
         print(json.dumps({"table1_fcg_iterations": bench_table1(torch, pmg)}), flush=True)
+        return 0
+    if args.hex_only:
+        print(json.dumps({"hex_general": bench_hex(torch, pmg, perfmodel, np, max(4, args.kernel_reps // 2))}),
+              flush=True)
         return 0
     dim, n, p, seed = HEADLINE
     dev = "cuda:0"
@@ -616,6 +716,8 @@ def main():
         log("bench: 16-problem batch (FP32-MG in FP64 CG) and the same solves one by one")
         out["batched"] = bench_batch(max(1, min(args.steps, 3)), torch, pmg, rhs_vector)
         out["batched_small"] = bench_small_batch(max(1, min(args.steps, 3)), torch, pmg, rhs_vector)
+    if not args.no_hex:
+        out["hex_general"] = bench_hex(torch, pmg, perfmodel, np, max(4, reps // 2))
     if args.extras:
         out["general_48_q6"] = bench_general(torch, pmg, max(1, min(args.steps, 2)))
     if not args.no_cpu_baseline:

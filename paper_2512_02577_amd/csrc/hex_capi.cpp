@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "hex_launch.h"
 #include "hex_setup.h"
 #include "launch.h"
 #include "pmg.h"
@@ -137,7 +138,7 @@ int upload(pmg_hex *hx, T **dst, const std::vector<T> &src) {
 // metric, element diagonals and per-patch inverse diagonals of every p-level
 int init_levels(pmg_hex *hx) {
   const HexHost &h = hx->h;
-  const int dim = h.dim, L = hx->nplev(), ncn = 1 << dim, nc = metric_components(dim);
+  const int dim = h.dim, L = hx->nplev(), ncn = 1 << dim;
   std::vector<const double *> B64, Dn64;
   int rc = PMG_OK;
   if ((rc = upload_qtabs(hx->allocs, hx->degrees, hx->qt64, hx->qt32, B64, Dn64))) return rc;
@@ -163,20 +164,21 @@ int init_levels(pmg_hex *hx) {
     PMG_TRY(launch_convert<float>(g64, g32, (long)ng, nullptr));
     hx->G64[l] = g64;
     hx->G32[l] = g32;
-    (void)nc;
     const long kd = dim == 3 ? (long)(q + 1) * (q + 1) * (q + 1) : (long)(q + 1) * (q + 1);
     const long e1 = 2 * q - 1, nip = dim == 3 ? e1 * e1 * e1 : e1 * e1;
-    double *cd, *i64;
+    double *i64;
     float *i32;
-    if ((rc = dev_alloc_in(hx->allocs, &cd, (size_t)(h.n_cells * kd))) ||
-        (rc = dev_alloc_in(hx->allocs, &i64, (size_t)(np * nip + 1))) ||
+    if ((rc = dev_alloc_in(hx->allocs, &i64, (size_t)(np * nip + 1))) ||
         (rc = dev_alloc_in(hx->allocs, &i32, (size_t)(np * nip + 1))))
       return rc;
+    double *cd = nullptr;  // element diagonals: setup only
+    PMG_HIP(hipMalloc((void **)&cd, (size_t)(h.n_cells * kd) * sizeof(double)));
     const double om = l == 0 ? 1.0 : hx->tab.omega[l];
     int krc = launch_cell_diag(dim, q, h.n_cells, B64[l], Dn64[l], g64, cd, nullptr);
     if (!krc) krc = launch_patch_invdiag_list<double>(dim, q, np, hx->pcells, om, cd, i64, nullptr);
     if (!krc) krc = launch_patch_invdiag_list<float>(dim, q, np, hx->pcells, om, cd, i32, nullptr);
     const hipError_t se = hipDeviceSynchronize();
+    (void)hipFree(cd);
     if (krc || se != hipSuccess) return fail(PMG_ERR_DEVICE, "diagonal setup failed: %s", hipGetErrorString(se));
     hx->invD64[l] = i64;
     hx->invD32[l] = i32;

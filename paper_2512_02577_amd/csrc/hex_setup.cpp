@@ -68,14 +68,21 @@ double center_det(int dim, const double *X) {  // X[corner * dim + axis], common
          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
-void group_by_color(const std::vector<int32_t> &color, int ncol, std::vector<int32_t> &list,
-                    std::vector<int32_t> &first) {
+// Items grouped by color; inside a color ordered by key (ties by index).  The order inside
+// a color does not change any result (items of one color touch disjoint outputs); ordering
+// by the smallest node an item touches lets neighbouring workgroups share cache lines when
+// the caller's numbering has locality.
+void group_by_color(const std::vector<int32_t> &color, int ncol, const std::vector<int32_t> &key,
+                    std::vector<int32_t> &list, std::vector<int32_t> &first) {
   first.assign(ncol + 1, 0);
   for (int32_t c : color) ++first[c + 1];
   for (int i = 0; i < ncol; ++i) first[i + 1] += first[i];
   list.assign(color.size(), 0);
   std::vector<int32_t> pos(first.begin(), first.end() - 1);
   for (size_t i = 0; i < color.size(); ++i) list[pos[color[i]]++] = (int32_t)i;
+  for (int c = 0; c < ncol; ++c)
+    std::sort(list.begin() + first[c], list.begin() + first[c + 1],
+              [&](int32_t a, int32_t b) { return key[a] != key[b] ? key[a] < key[b] : a < b; });
 }
 
 }  // namespace
@@ -393,7 +400,13 @@ int hex_build(int dim, int p, long nv, const double *xyz, long nc, const int32_t
     l.erase(std::unique(l.begin(), l.end()), l.end());
   }
   const int npc = dsatur(adj, h.pcolor);
-  group_by_color(h.pcolor, npc, h.plist, h.pfirst);
+  std::vector<int32_t> key(np, INT32_MAX);
+  for (long q = 0; q < np; ++q)
+    for (int e = 0; e < Nd; ++e) {
+      const int32_t d = h.pmap[(size_t)q * Nd + e];
+      if (d >= 0 && d < key[q]) key[q] = d;
+    }
+  group_by_color(h.pcolor, npc, key, h.plist, h.pfirst);
   std::vector<std::vector<int32_t>> cadj(nc);
   for (long c = 0; c < nc; ++c) {
     for (int j = 0; j < ncn; ++j) {
@@ -405,7 +418,10 @@ int hex_build(int dim, int p, long nv, const double *xyz, long nc, const int32_t
     cadj[c].erase(std::unique(cadj[c].begin(), cadj[c].end()), cadj[c].end());
   }
   const int ncc = dsatur(cadj, h.ccolor);
-  group_by_color(h.ccolor, ncc, h.clist, h.cfirst);
+  key.assign(nc, INT32_MAX);
+  for (long c = 0; c < nc; ++c)
+    for (int e = 0; e < kd; ++e) key[c] = std::min(key[c], h.cdofs[(size_t)c * kd + e]);
+  group_by_color(h.ccolor, ncc, key, h.clist, h.cfirst);
   return 0;
 }
 

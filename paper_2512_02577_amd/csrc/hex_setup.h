@@ -22,7 +22,7 @@ struct HexHost {
   std::vector<int32_t> pcells;   // per patch: 2^d cells, block position dx + 2 dy + 4 dz
   std::vector<int32_t> pmap;     // per patch: (2p+1)^d closure nodes, x fastest; -1 on the boundary
   std::vector<int32_t> pcolor, ccolor;
-  std::vector<int32_t> plist, clist;  // patches / cells grouped by color, ascending inside a color
+  std::vector<int32_t> plist, clist;  // patches / cells grouped by color, inside a color by smallest node
   std::vector<int32_t> pfirst, cfirst;  // offsets of the colors in plist / clist (n_colors + 1)
   int reflected = 0;             // 1 if the common frame was mirrored to make det J > 0
 };

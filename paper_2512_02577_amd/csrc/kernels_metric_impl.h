@@ -8,6 +8,7 @@
 
 #include "bodies_metric.h"
 #include "dispatch.h"
+#include "hex_launch.h"
 #include "launch.h"
 
 namespace pmg {

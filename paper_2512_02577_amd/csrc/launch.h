@@ -61,20 +61,6 @@ struct MetricLaunchers {
   static int apply_init(int m, bool resid, const T *b, const T *u, T *out, hipStream_t s);
 };
 
-// Launchers of general hex meshes with stored maps (metric stored in the compute type);
-// instantiated in kernels_hex_*.hip for (3D, 2D) x (double, float).
-template <int DIM, typename T>
-struct HexLaunchers {
-  static size_t patch_bytes(int p);
-  static size_t apply_bytes(int p);
-  // one color: a.plist holds its a.n_patch patches
-  static int smooth(int p, const MetricSmoothArgs<T, T> &a, const Arena &ar, hipStream_t s);
-  // one color: a.clist holds its a.n_cells cells
-  static int apply(int p, const MetricApplyArgs<T, T> &a, const Arena &ar, hipStream_t s);
-  static int apply_init(long n_dofs, bool resid, const unsigned char *bnd, const T *b, const T *u, T *out,
-                        hipStream_t s);
-};
-
 // Setup and coarse-solve kernels of the general path (setup.hip).
 // cdiag[cell * (q+1)^d + node] = diagonal of the element matrix of degree q (metric G, FP64)
 int launch_cell_diag(int dim, int q, long n_cells, const double *B, const double *Dn, const double *G, double *cdiag,
@@ -82,10 +68,6 @@ int launch_cell_diag(int dim, int q, long n_cells, const double *B, const double
 // invD[patch * (2q-1)^d + e] = omega / (patch diagonal), stored as S
 template <typename S>
 int launch_patch_invdiag(int dim, int q, int n, double omega, const double *cdiag, S *invD, hipStream_t s);
-// the same for the stored patch cell lists of a general hex mesh (np patches)
-template <typename S>
-int launch_patch_invdiag_list(int dim, int q, long np, const int32_t *pcells, double omega, const double *cdiag,
-                              S *invD, hipStream_t s);
 int launch_set_identity(double *A, int m, hipStream_t s);
 // z = Ainv r on interior nodes of an m0^d interior grid (total nodes per direction mt),
 // z = r on boundary nodes; w is a work vector of m interior entries

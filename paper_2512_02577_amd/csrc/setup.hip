@@ -2,6 +2,7 @@
 // conversions) and the dense coarse solve.
 #include <hip/hip_runtime.h>
 
+#include "hex_launch.h"
 #include "launch.h"
 
 namespace pmg {

@@ -95,14 +95,15 @@ def _cube_symmetries(dim: int) -> list[tuple[tuple[int, ...], tuple[int, ...]]]:
 
 
 def hex_mesh(dim: int, n: int, p: int, seed: int, shape: str = "L", distortion: float = 0.0,
-             permute: bool = True, orient: bool = True) -> dict:
+             permute: bool = True, orient: bool = True, renumber_nodes: bool = True) -> dict:
     """A general hex (2D: quad) mesh of degree-p nodes given as cell lists.
 
     The cells are the unit voxels of an n^dim lattice that belong to the domain:
     "box" keeps all, "L" drops those with x >= n/2 and y >= n/2, "hole" drops an inner
     block [n/4, 3n/4)^dim (a cavity with its own boundary).  Each vertex moves by
-    distortion * (uniform[-1/2, 1/2]^dim) / n.  With `permute`, vertices, cells and nodes
-    are numbered in a random order; with `orient`, every cell lists its corners and nodes
+    distortion * (uniform[-1/2, 1/2]^dim) / n.  With `permute`, vertices, cells and (unless
+    renumber_nodes is False, which keeps the lattice order of the nodes, as a numbering with
+    locality) nodes are numbered in a random order; with `orient`, every cell lists its corners and nodes
     in the lexicographic order (x fastest) of a randomly rotated and reflected local
     frame.  Returns a dict with
       vertices       (n_vertices, dim) float64
@@ -139,7 +140,7 @@ def hex_mesh(dim: int, n: int, p: int, seed: int, shape: str = "L", distortion: 
     nu = np.unique(nkeys)
     jitter = distortion * rng.uniform(-0.5, 0.5, (len(vu), dim)) / n  # drawn first: same geometry either way
     vperm = rng.permutation(len(vu)) if permute else np.arange(len(vu))
-    nperm = rng.permutation(len(nu)) if permute else np.arange(len(nu))
+    nperm = rng.permutation(len(nu)) if permute and renumber_nodes else np.arange(len(nu))
     cell_vertices = vperm[np.searchsorted(vu, vkeys)].astype(np.int32)
     cell_dofs = nperm[np.searchsorted(nu, nkeys)].astype(np.int32)
     # vertex coordinates on the lattice, then jitter

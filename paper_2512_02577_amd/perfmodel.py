@@ -109,3 +109,26 @@ def smooth_launch_patches(dim: int, n: int, color: int) -> int:
 
 def apply_bytes(dim: int, n: int, p: int, word: int = 8) -> int:
     return 2 * word * (p * n + 1) ** dim
+
+
+def hex_smooth_bytes(dim: int, p: int, degrees: list[int], n_patches: int, word: int = 8, index: int = 4) -> int:
+    """Bytes one application of the stored-map smoother moves, summed over its patches
+    (patches of one color share no cell, so nothing a launch reads is read twice by it):
+    the patch's closure map and cell list, u on the closure, b and u on the interior, u
+    written on the interior, and on every p-level the metric of the patch's 2^d cells at
+    their Gauss points and the patch's inverse diagonal."""
+    comp = 6 if dim == 3 else 3
+    N, n = 2 * p + 1, 2 * p - 1
+    per = index * (N ** dim + 2 ** dim) + word * (N ** dim + 3 * n ** dim)
+    for q in degrees:
+        per += word * (2 ** dim * comp * (q + 1) ** dim + (2 * q - 1) ** dim)
+    return per * n_patches
+
+
+def hex_apply_bytes(dim: int, p: int, n_cells: int, n_dofs: int, word: int = 8, index: int = 4) -> int:
+    """Bytes of the stored-map apply: the init pass (u read, out written, boundary flag per
+    node) and per cell its node map, u on its nodes, out read and written on its nodes
+    and the metric at its Gauss points."""
+    comp = 6 if dim == 3 else 3
+    kd = (p + 1) ** dim
+    return n_dofs * (2 * word + 1) + n_cells * (index * kd + 3 * word * kd + word * comp * kd)
