@@ -52,6 +52,8 @@ def cd(a):
                                      (3, 4, 3), (3, 3, 4), (3, 5, 4), (3, 6, 4), (3, 3, 5), (3, 4, 5), (3, 2, 6), (3, 2, 7),
                                      (3, 2, 8), (3, 17, 1), (3, 9, 2)])
 def test_apply_residual_and_mass(emu, dim, n, p, lanes):
+    if p == 8 and lanes == 0:
+        pytest.skip("degree 8 runs at the library's lane count only (the one-lane emulation takes seconds)")
     # the 3D degrees 1-5 run the marching apply; n = 17 (p = 1) and 9 (p = 2) leave a partial
     # xy tile, n = 5 (p = 4) one at the upper end with the extra boundary row; zsplit 1 walks
     # every layer in one workgroup, 0 takes the library's z segments
@@ -161,7 +163,7 @@ def test_direct_and_reinforced_smoother(emu, dim, n, p, lv):
     cases = [("direct", "jacobi", [1.0] * len(deg), 2, 0, 1),
              ("half", "reinforced", om_r, 0, 1, 1), ("full", "reinforced", om_r, 1, 1, 1),
              ("half", "reinforced", om_r, 0, 1, 2)]
-    for local, sm, om, code, reinf, it in cases:
+    for local, sm, om, code, reinf, it in cases if p < 8 else cases[:2]:  # degree 8: the oracle takes ~20 s a case
         ls = LevelSmoother(StructuredMesh(dim, n), deg, omega=om, local=local, smoother=sm, n_local_iter=it)
         # degree 8: the library's lane count only (each oracle sweep there takes seconds)
         for direction, lanes in ((1, 1), (-1, 2), (1, 0)) if p < 8 else ((1, 1),):
