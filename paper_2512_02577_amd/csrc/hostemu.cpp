@@ -11,7 +11,8 @@
 //
 // Lane codes of the entry points: 0 = one lane; 1 = the lane count of the library's
 // launch of that body (patch_threads, apply_threads, ...); 2 = 256 lanes (the latency
-// variant of the patch smoother).  Table modes: 0 = every 1D table in its own exactly sized
+// variant of the patch smoother); 3 = one wave of 64 lanes (the patch smoother's one-wave
+// kernel of large launches).  Table modes: 0 = every 1D table in its own exactly sized
 // vector; 1 = the library's concatenated table block (tab_layout.h).
 #include <pthread.h>
 
@@ -182,6 +183,8 @@ struct EmuSmooth {
                          : go<patch_threads(P, DIM), false>(base, n, color_dir, local_only, n_blocks);
         case 2: return o ? go<256, true>(base, n, color_dir, local_only, n_blocks)
                          : go<256, false>(base, n, color_dir, local_only, n_blocks);
+        case 3: return o ? go<64, true>(base, n, color_dir, local_only, n_blocks)
+                         : go<64, false>(base, n, color_dir, local_only, n_blocks);
         default: return -1;
       }
     }

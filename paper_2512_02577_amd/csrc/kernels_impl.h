@@ -38,6 +38,14 @@ __global__ __launch_bounds__(256) void k_smooth_w(SmoothArgs<T> a) {
   B::template smooth_patch<ONE>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
+// One wave per patch, for the largest launches of the default local solver where the
+// per-degree count is two waves (3D degree 4).
+template <int DIM, typename T, int P, class H>
+__global__ __launch_bounds__(64) void k_smooth_1w(SmoothArgs<T> a) {
+  using B = PatchBody<DIM, T, 64, P, H>;
+  B::template smooth_patch<true>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
+}
+
 template <int DIM, typename T, int P, class H>
 __global__ __launch_bounds__(patch_threads(P, DIM, sizeof(T))) void k_smooth_g(SmoothArgs<T> a, void *garena) {
   using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
@@ -139,8 +147,15 @@ struct SmoothL {
         using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
         const size_t bytes = B::arena(a.n_iter) * sizeof(T);
         const bool one = a.full == 0 && a.n_iter == 1 && a.direct == 0 && a.reinf == 0;
-        // patch_lanes: 0 by launch size, 1 always the per-degree count, 2 always 256
+        // patch_lanes: 0 by launch size, 1 always the per-degree count, 2 always 256, 3 one
+        // wave where the degree has a one-wave variant (else the per-degree count)
         const bool wide = ar.patch_lanes == 2 || (ar.patch_lanes == 0 && a.n_patch <= kWideLaunch * ar.ncu);
+        if constexpr (DIM == 3 && patch_threads(P, DIM, sizeof(T)) == 128) {
+          const bool wave =
+              ar.patch_lanes == 3 || (ar.patch_lanes == 0 && sizeof(T) == 4 && a.n_patch >= kWaveLaunch * ar.ncu);
+          if (one && wave && bytes <= ar.lds_max)
+            return launch_arena(k_smooth_1w<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, 64, bytes, ar, s, a);
+        }
         if constexpr (patch_threads(P, DIM, sizeof(T)) < 256)
           if (wide && bytes <= ar.lds_max)
             return one ? launch_arena(k_smooth_w<DIM, T, P, H, true>, k_smooth_g<DIM, T, P, H>, a.n_patch, 256,

@@ -23,6 +23,14 @@ struct Arena {
 // (unless the problem's configuration fixes the lane count).
 constexpr int kWideLaunch = 4;
 
+// FP32 launches of the 3D degree-4 default-solver kernel with at least this many patches per
+// CU run one wave per patch (unless the configuration fixes the lane count): the FP32 arena
+// lets 24 patches share a CU, which two waves per patch would cap at 16 (32 waves per CU),
+// and fewer lanes per patch leave fewer of them idle in the short contraction stages.
+// Smaller launches keep two waves per patch, which finish each patch sooner; FP64 patches
+// (12 per CU by LDS whatever their lane count) measured the same either way and keep two.
+constexpr int kWaveLaunch = 64;
+
 // Bytes of LDS a workgroup may use on the current device (queried once per process).
 inline size_t device_lds_limit() {
   static const size_t v = [] {

@@ -2,12 +2,16 @@
 (Alg. 1 with the local p-multigrid of Alg. 2/3), and the errors of FP32 multigrid against
 the FP64 oracle per degree.
 
-A color launch runs the per-degree lane count (64 lanes for p <= 2, 128 for p <= 4, 256
-above) or the 256-lane latency variant, each either in the variant compiled for the default
-local solver (one half V-cycle, one Richardson step) or in the general one.  Large problems
-take the per-degree width, small ones the latency variant; the configuration fixes one or
-the other here so that small meshes the oracle finishes in seconds reach both, and one
-natural case has more than 1,024 patches per color (the per-degree width at full size).
+A color launch runs the per-degree lane count (64 lanes for p <= 3, 128 for p = 4, 256
+or 512 above) or the 256-lane latency variant, each either in the variant compiled for the
+default local solver (one half V-cycle, one Richardson step) or in the general one; 3D
+degree-4 FP32 colors of at least 64 patches per CU run the default solver on one wave per
+patch (the configuration can force that kernel in both precisions).
+Large problems take the per-degree width (or the one-wave kernel), small ones the latency
+variant; the configuration fixes one of them here so that small meshes the oracle finishes
+in seconds reach each, and one natural case has more than 1,024 patches per color (the
+per-degree width at full size).  At 64^3 Q4 the one-wave kernel that the benchmark's
+finest level runs is compared with the per-degree width on the same inputs.
 
 Tolerances as in test_gpu_parity.py: FP64 smoother / V-cycle 1e-11, FP32 2e-4 (max-norm
 relative to the oracle's result).
@@ -68,9 +72,14 @@ WIDTH_CASES = [(3, 5, 1, None), (3, 5, 2, None), (3, 4, 3, None), (3, 4, 4, None
 SOLVERS = [("half", 1), ("full", 1), ("half", 2)]  # the first is the default solver's own variant
 
 
-@pytest.mark.parametrize("lanes", [pmg.LANES_NARROW, pmg.LANES_WIDE])
-@pytest.mark.parametrize("dim,n,p,lv", WIDTH_CASES)
-def test_smoother_widths_fp64(dim, n, p, lv, lanes):
+# the one-wave kernel exists for 3D degree 4 only (elsewhere LANES_WAVE is the per-degree count)
+WIDTH_PARAMS = [(c, lanes) for c in WIDTH_CASES for lanes in (pmg.LANES_NARROW, pmg.LANES_WIDE)] + \
+    [(c, pmg.LANES_WAVE) for c in WIDTH_CASES if c[0] == 3 and c[2] == 4]
+
+
+@pytest.mark.parametrize("case,lanes", WIDTH_PARAMS)
+def test_smoother_widths_fp64(case, lanes):
+    dim, n, p, lv = case
     print(f"case smoother widths dim {dim} n {n} p {p} levels {lv} lanes {lanes}", flush=True)
     deg = lv or p_hierarchy(p)
     om = omega_of(len(deg))
@@ -86,8 +95,8 @@ def test_smoother_widths_fp64(dim, n, p, lv, lanes):
             assert relerr(host(ud), ref) <= 1e-11, (local, it, direction)
 
 
-@pytest.mark.parametrize("lanes", [pmg.LANES_NARROW, pmg.LANES_WIDE])
-@pytest.mark.parametrize("dim,n,p", [(3, 5, 2), (3, 4, 4), (2, 7, 3)])
+@pytest.mark.parametrize("dim,n,p,lanes", [(d, n, p, l) for (d, n, p) in [(3, 5, 2), (3, 4, 4), (2, 7, 3)]
+                                             for l in (pmg.LANES_NARROW, pmg.LANES_WIDE)] + [(3, 4, 4, pmg.LANES_WAVE)])
 def test_smoother_widths_fp32(dim, n, p, lanes):
     print(f"case smoother widths fp32 dim {dim} n {n} p {p} lanes {lanes}", flush=True)
     deg = p_hierarchy(p)
@@ -131,6 +140,27 @@ def test_smoother_natural_full_width_launch(name, p, direction, seeds):
     ud = dev(u0)
     pmg.smooth(pr, pr.finest, ud, dev(b), direction)
     assert sampled_relerr(host(ud), ref) <= 1e-11
+
+
+def test_one_wave_kernel_at_the_benchmark_size():
+    # 64^3 cells, Q4 (16,974,593 nodes): every color has more than 64 patches per CU, so the
+    # default configuration runs the one-wave kernel in FP32 (forced here for FP64 too); the
+    # per-degree width (compared with the oracle above and at 24^3) on the same inputs must
+    # give the same sweep up to the rounding of the coarsest p-level's block sum, in both
+    # directions and both precisions
+    dim, n, p = 3, 64, 4
+    print("case one-wave kernel 64^3 Q4 against the per-degree width", flush=True)
+    auto, narrow = make(dim, n, p, lanes=pmg.LANES_WAVE), make(dim, n, p, lanes=pmg.LANES_NARROW)
+    b = rhs_vector(dim, n, p, 53)
+    u0 = np.random.default_rng(54).uniform(-1, 1, len(b))
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        bd = dev(b, dtype)
+        for direction in (1, -1):
+            ua, un = dev(u0, dtype), dev(u0, dtype)
+            pmg.smooth(auto, auto.finest, ua, bd, direction)
+            pmg.smooth(narrow, narrow.finest, un, bd, direction)
+            assert relerr(host(ua), host(un)) <= tol, (dtype, direction)
+            assert relerr(host(ua), u0) > 1e-3  # the sweep changed the iterate
 
 
 @pytest.mark.parametrize("p", [5, 7])
