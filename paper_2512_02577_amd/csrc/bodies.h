@@ -80,15 +80,19 @@ struct PatchBody {
   static constexpr int ndl(int l) { return ipow(2 * H::q[l] - 1, DIM); }
 
   // ---- LDS layout (every contraction that shrinks a tensor runs in place) ----
-  // phase R (patch residual): r | closure tensor (stage outputs A, C in place) | B, G
+  // phase R (patch residual): r | closure tensor (2D) or Zm = Mz u (3D; stage outputs in
+  //                           place) | B (2D) or Zk = Kz u (3D)
   // phase S (local solve):    r | d | partial sums | r_l, d_l of levels L-2 .. 1 | X (2 nd) | cc
   // X holds a level's vmult pair (A, B; the residual lands on A in place), the in-place
   // restriction of that residual, and the two stages of a prolongation.  cc (the
   // correction of Richardson steps after the first) is at the end, so that one step
   // needs only `size1`.
+  // One half V-cycle alone (the default local solver's own kernels, ONE) reads r last in
+  // the top level's residual; the lower levels' r_l, d_l then take r's place when they
+  // fit there (layout A):  r, later r_l, d_l of levels L-2 .. 1 | d | partial sums | X.
   static constexpr int off_r = 0;  // patch residual, then running Richardson residual
   static constexpr int off_ucl = nd;
-  static constexpr int off_B = nd + Nd;
+  static constexpr int off_B = nd + (DIM == 3 ? n * N * N : Nd);
   static constexpr int phaseR_end = off_B + (DIM == 3 ? n * N * N : n * N);
   static constexpr int off_d = nd;
   static constexpr int NRED = 8;  // per-wave partial sums of block_sum (up to 8 waves)
@@ -101,17 +105,26 @@ struct PatchBody {
   static constexpr int size1 = cmax(phaseR_end, phaseS_end);
   static constexpr int off_cc = size1;
   static constexpr int size = size1 + nd;
+  static constexpr bool ALIAS = lower_size(L - 2) <= nd;  // layout A possible
+  template <bool A>
+  static constexpr int offX() { return A ? 2 * nd + NRED : off_X; }
+  template <bool A>
+  static constexpr int offLR(int l) { return A ? lower_size(l - 1) : off_lr(l); }
+  template <bool A>
+  static constexpr int offLD(int l) { return offLR<A>(l) + ndl(l); }
+  // arena of the ONE kernels
+  static constexpr int size_one = ALIAS ? cmax(phaseR_end, offX<true>() + 2 * nd) : size1;
   static_assert(NT <= 64 * NRED, "block_sum scratch");
 
   // res = r - c A_l d on p-level l (interior patch operator); A, B scratch in X, res may
   // be X itself (the last stage lands on A in place) or r
-  template <int l>
+  template <int l, bool AL = false>
   PMG_INLINE static void vmult_residual(int tid, T *lds, const DevTabs<T> &tb, T c, const T *d, const T *r,
                                         T *res) {
     constexpr int m = nl(l);
     using Pat = PatInterior<qd(l)>;
     using D = Dense<m, m>;
-    T *A = lds + off_X, *B = lds + off_X + ndl(l);
+    T *A = lds + offX<AL>(), *B = lds + offX<AL>() + ndl(l);
     if constexpr (DIM == 3) {
       scontract2<0, m, m, m, Pat, NT, D, D, D>(tid, d, A, tb.Mp[l], B, tb.Kp[l]);  // A = Mx d, B = Kx d
       PMG_SYNC();
@@ -222,7 +235,8 @@ struct PatchBody {
   // reinf: the p-level Richardson steps use the Cartesian-reinforced preconditioner (on the
   // Cartesian path the inverse of the patch operator by fast diagonalization, damped by
   // om[l]) instead of damped Jacobi
-  template <int l>
+  // AL: layout A (one half V-cycle alone; r is not read after this level's residual)
+  template <int l, bool AL = false>
   PMG_INLINE static void cycle(int tid, T *lds, const DevTabs<T> &tb, T c, T cinv, const T *r, T *d,
                                bool full, const PreD *pre = nullptr, bool reinf = false,
                                Omega<T> om = Omega<T>{}) {
@@ -252,8 +266,8 @@ struct PatchBody {
         }
       }
       PMG_SYNC();
-      T *res = lds + off_X;
-      vmult_residual<l>(tid, lds, tb, c, d, r, res);  // res = r - A d
+      T *res = lds + offX<AL>();
+      vmult_residual<l, AL>(tid, lds, tb, c, d, r, res);  // res = r - A d
       PMG_SYNC();
       if constexpr (l == 1) {
         // the coarsest p-level has one node: restriction is a weighted sum, its exact
@@ -277,8 +291,8 @@ struct PatchBody {
         using PP = PatProlong<q, qc>;
         using D = Dense<m, m>;
         using DC = Dense<mc, mc>;
-        T *rc = lds + off_lr(l - 1), *dc = lds + off_ld(l - 1);
-        T *X0 = lds + off_X, *X1 = lds + off_X + nd;
+        T *rc = lds + offLR<AL>(l - 1), *dc = lds + offLD<AL>(l - 1);
+        T *X0 = lds + offX<AL>(), *X1 = lds + offX<AL>() + nd;
         if constexpr (DIM == 3) {
           scontract1<0, m, m, m, PR, NT, false, D, D, true>(tid, res, res, tb.TpT[l]);
           PMG_SYNC();
@@ -291,7 +305,7 @@ struct PatchBody {
           scontract1<1, mc, m, 1, PR, NT, false, D, DC>(tid, res, rc, tb.TpT[l]);
         }
         PMG_SYNC();
-        cycle<l - 1>(tid, lds, tb, c, cinv, rc, dc, full, pre, reinf, om);
+        cycle<l - 1, AL>(tid, lds, tb, c, cinv, rc, dc, full, pre, reinf, om);
         if constexpr (DIM == 3) {  // d += P dc
           scontract1<0, mc, mc, mc, PP, NT, false, DC, Dense<m, mc>>(tid, dc, X0, tb.Tp[l]);
           PMG_SYNC();
@@ -305,8 +319,8 @@ struct PatchBody {
         }
         PMG_SYNC();
       }
-      if (full) {  // post-smoothing
-        vmult_residual<l>(tid, lds, tb, c, d, r, res);
+      if (!AL && full) {  // post-smoothing (layout A has overwritten r: half V-cycles only)
+        vmult_residual<l, AL>(tid, lds, tb, c, d, r, res);
         PMG_SYNC();
         if (reinf) {
           T *tmp = res + ndq;  // the vmult's second stage buffer, dead now
@@ -329,7 +343,7 @@ struct PatchBody {
   PMG_INLINE static void local_solve(int tid, T *lds, const SmoothArgs<T> &a, const PreD *pre = nullptr) {
     T *r = lds + off_r, *d = lds + off_d, *cc = lds + off_cc;
     if constexpr (ONE) {
-      cycle<L - 1>(tid, lds, a.tb, a.c, a.cinv, r, d, false, pre);
+      cycle<L - 1, ALIAS>(tid, lds, a.tb, a.c, a.cinv, r, d, false, pre);
       return;
     }
     if constexpr (L >= 2) {
@@ -350,8 +364,9 @@ struct PatchBody {
     }
   }
 
-  // Arena elements for n_iter Richardson steps.
+  // Arena elements for n_iter Richardson steps, and of the ONE kernels.
   PMG_HD static constexpr int arena(int n_iter) { return n_iter > 1 ? size : size1; }
+  PMG_HD static constexpr int arena_one() { return size_one; }
 
   PMG_INLINE static void decode(int idx, int k[3]) {
     k[0] = idx % n;

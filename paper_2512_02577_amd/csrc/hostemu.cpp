@@ -155,7 +155,8 @@ struct EmuSmooth {
     template <int NT, bool ONE>
     static int go(const SmoothArgs<double> &base, int n, int color_dir, bool local_only, int n_blocks) {
       using B = PatchBody<DIM, double, NT, P, H>;
-      std::vector<double> lds(B::arena(base.n_iter));  // exactly what the device launch gets
+      // exactly what the device launch gets
+      std::vector<double> lds(ONE && !local_only ? B::arena_one() : B::arena(base.n_iter));
       if (local_only) {
         launch<NT>(n_blocks, lds, [&](int tid, int blk, double *ar) { B::local_only(tid, blk, ar, base); });
         return 0;

@@ -145,8 +145,8 @@ struct SmoothL {
     struct F {
       static int run(const SmoothArgs<T> &a, const Arena &ar, hipStream_t s) {
         using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
-        const size_t bytes = B::arena(a.n_iter) * sizeof(T);
         const bool one = a.full == 0 && a.n_iter == 1 && a.direct == 0 && a.reinf == 0;
+        const size_t bytes = (one ? B::arena_one() : B::arena(a.n_iter)) * sizeof(T);
         // patch_lanes: 0 by launch size, 1 always the per-degree count, 2 always 256, 3 one
         // wave where the degree has a one-wave variant (else the per-degree count)
         const bool wide = ar.patch_lanes == 2 || (ar.patch_lanes == 0 && a.n_patch <= kWideLaunch * ar.ncu);
