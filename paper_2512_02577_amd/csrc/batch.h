@@ -112,11 +112,13 @@ template <> struct PaperH<8> { using type = Degrees<1, 3, 7, 8>; };
 // is created) and are read through the constant address space.
 template <typename T>
 struct BatchLaunch {
-  static size_t smooth_bytes(int p, int n_iter);  // dynamic LDS of the patch kernel
+  // dynamic LDS of the patch kernel (one: the kernel of the default local solver alone)
+  static size_t smooth_bytes(int p, int n_iter, bool one = false);
   static size_t apply_bytes(int p, int tile);
   // every segment of a smooth or apply stage table has degree p (one kernel per degree,
-  // shaped like the single-problem kernel of that degree); tile: batch_tile option
-  static int smooth(const BSmoothStage<T> *st_dev, int p, int grid, size_t shmem, hipStream_t s);
+  // shaped like the single-problem kernel of that degree); tile: batch_tile option; one:
+  // every segment has the default local solver (one half V-cycle, one Richardson step)
+  static int smooth(const BSmoothStage<T> *st_dev, int p, bool one, int grid, size_t shmem, hipStream_t s);
   static int apply(const BApplyStage<T> *st_dev, int p, int tile, bool resid, int grid, size_t shmem, hipStream_t s);
   static int pass(const BPassStage<T> *st_dev, int grid, hipStream_t s);
   static int coarse(const BCoarseStage<T> *st_dev, int nseg, hipStream_t s);

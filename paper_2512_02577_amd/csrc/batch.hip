@@ -46,8 +46,10 @@ __device__ inline int opaque_tid() {
 }
 
 // One kernel per degree: the patch body of the single-problem kernel (same threads per
-// workgroup, same registers) inside a loop over the work items of every segment.
-template <typename T, int P>
+// workgroup, same registers) inside a loop over the work items of every segment.  ONE: every
+// segment of the stage has the default local solver (one half V-cycle, one Richardson step),
+// so the body compiled for it alone runs, with its smaller arena.
+template <typename T, int P, bool ONE>
 __global__ __launch_bounds__(patch_threads(P, 3, sizeof(T))) void k_bsmooth(const BSmoothStage<T> *st_) {
   using B = PatchBody<3, T, patch_threads(P, 3, sizeof(T)), P, typename PaperH<P>::type>;
   const cptr<BSmoothStage<T>> st = as_const(st_);
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(patch_threads(P, 3, sizeof(T))) void k_bsmooth(cons
     if (!as_const(st->active)[st->seg[s].prob]) continue;
     const int local = blk - st->seg[s].start;
     if (local >= st->seg[s].a.n_patch) continue;  // padding of the segment to a multiple of 8
-    B::smooth_patch(opaque_tid<patch_threads(P, 3, sizeof(T))>(), local, lds, table_ref(st->seg[s].a));
+    B::template smooth_patch<ONE>(opaque_tid<patch_threads(P, 3, sizeof(T))>(), local, lds, table_ref(st->seg[s].a));
     __syncthreads();
   }
 }
@@ -175,8 +177,9 @@ template <typename T>
 struct SmoothBytes {
   template <int P>
   struct F {
-    static int run(int n_iter, size_t *o) {
-      *o = PatchBody<3, T, patch_threads(P, 3, sizeof(T)), P, typename PaperH<P>::type>::arena(n_iter) * sizeof(T);
+    static int run(int n_iter, bool one, size_t *o) {
+      using B = PatchBody<3, T, patch_threads(P, 3, sizeof(T)), P, typename PaperH<P>::type>;
+      *o = (one ? B::arena_one() : B::arena(n_iter)) * sizeof(T);
       return 0;
     }
   };
@@ -295,9 +298,9 @@ __global__ __launch_bounds__(kT) void k_bvec_final(const BVecStage *st_, int op)
 }  // namespace
 
 template <typename T>
-size_t BatchLaunch<T>::smooth_bytes(int p, int n_iter) {
+size_t BatchLaunch<T>::smooth_bytes(int p, int n_iter, bool one) {
   size_t o = 0;
-  return dispatch_degree<SmoothBytes<T>::template F>(p, n_iter, &o) == 0 ? o : 0;
+  return dispatch_degree<SmoothBytes<T>::template F>(p, n_iter, one, &o) == 0 ? o : 0;
 }
 
 template <typename T>
@@ -312,7 +315,8 @@ struct KernelTable {
   template <int P>
   struct F {
     static int run(const void **sm, const void **ap) {
-      *sm = (const void *)k_bsmooth<T, P>;
+      sm[0] = (const void *)k_bsmooth<T, P, false>;
+      sm[1] = (const void *)k_bsmooth<T, P, true>;
       ap[0] = (const void *)k_bmarch<T, P, false>;
       ap[1] = (const void *)k_bmarch<T, P, true>;
       ap[2] = (const void *)k_bapply<T, P, 1, false>;
@@ -326,21 +330,23 @@ template <typename T>
 int BatchLaunch<T>::prepare(size_t shmem) {
   if (shmem <= 65536) return 0;
   for (int p = 1; p <= kMaxDegree; ++p) {
-    const void *sm = nullptr, *ap[4] = {};
-    if (dispatch_degree<KernelTable<T>::template F>(p, &sm, ap) != 0) return -2;
-    for (const void *k : {sm, ap[0], ap[1], ap[2], ap[3]})
+    const void *sm[2] = {}, *ap[4] = {};
+    if (dispatch_degree<KernelTable<T>::template F>(p, sm, ap) != 0) return -2;
+    for (const void *k : {sm[0], sm[1], ap[0], ap[1], ap[2], ap[3]})
       if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess) return -4;
   }
   return 0;
 }
 
 template <typename T>
-int BatchLaunch<T>::smooth(const BSmoothStage<T> *st, int p, int grid, size_t shmem, hipStream_t s) {
+int BatchLaunch<T>::smooth(const BSmoothStage<T> *st, int p, bool one, int grid, size_t shmem, hipStream_t s) {
   if (grid <= 0) return 0;
-  const void *sm = nullptr, *ap[4] = {};
-  if (dispatch_degree<KernelTable<T>::template F>(p, &sm, ap) != 0) return -2;
+  const void *sm[2] = {}, *ap[4] = {};
+  if (dispatch_degree<KernelTable<T>::template F>(p, sm, ap) != 0) return -2;
   void *args[] = {(void *)&st};
-  if (hipLaunchKernel(sm, dim3(grid), dim3(patch_threads(p, 3, sizeof(T))), args, shmem, s) != hipSuccess) return -4;
+  if (hipLaunchKernel(sm[one ? 1 : 0], dim3(grid), dim3(patch_threads(p, 3, sizeof(T))), args, shmem, s) !=
+      hipSuccess)
+    return -4;
   return 0;
 }
 
@@ -348,8 +354,8 @@ template <typename T>
 int BatchLaunch<T>::apply(const BApplyStage<T> *st, int p, int tile, bool resid, int grid, size_t shmem,
                           hipStream_t s) {
   if (grid <= 0) return 0;
-  const void *sm = nullptr, *ap[4] = {};
-  if (dispatch_degree<KernelTable<T>::template F>(p, &sm, ap) != 0) return -2;
+  const void *sm[2] = {}, *ap[4] = {};
+  if (dispatch_degree<KernelTable<T>::template F>(p, sm, ap) != 0) return -2;
   void *args[] = {(void *)&st};
   const int threads = tile != 0 ? apply_threads(p) : march_threads(p);
   if (hipLaunchKernel(ap[2 * (tile != 0) + (resid ? 1 : 0)], dim3(grid), dim3(threads), args, shmem, s) != hipSuccess)

@@ -35,6 +35,7 @@ enum Kind { K_SMOOTH = 0, K_APPLY, K_PASS, K_COARSE, K_ELEM };
 // concurrently.
 struct Step {
   int kind = 0, p = 0, tile = 0, resid = 0, group = 0;  // p: degree of smooth and apply steps
+  int one = 0;  // smooth step whose segments all have the default local solver
   size_t off = 0;    // byte offset of the stage table in the plan's device buffer
   long items = 0;    // workgroups of work: patches, tiles, or 256-thread blocks
   size_t shmem = 0;  // dynamic LDS of the launch
@@ -248,9 +249,15 @@ struct Builder {
       st[p].total = tot[p];
       st[p].active = bt->active;
       int iters = 1;
-      for (int k = 0; k < st[p].nseg; ++k) iters = std::max(iters, st[p].seg[k].a.n_iter);
+      bool one = true;
+      for (int k = 0; k < st[p].nseg; ++k) {
+        const SmoothArgs<T> &a = st[p].seg[k].a;
+        iters = std::max(iters, a.n_iter);
+        one = one && a.full == 0 && a.n_iter == 1 && a.direct == 0 && a.reinf == 0;
+      }
       push(K_SMOOTH, p, 0, 0, put(pl.blob, st[p], used_bytes<BSmoothStage<T>, BSmoothSeg<T>>(st[p].nseg)), tot[p],
-           BatchLaunch<T>::smooth_bytes(p, iters));
+           BatchLaunch<T>::smooth_bytes(p, iters, one));
+      pl.steps.back().one = one;
       any = true;
     }
     if (any) ++group;
@@ -487,7 +494,7 @@ template <typename T>
 int launch_step(const Plan<T> &pl, const Step &s, hipStream_t st) {
   const void *tab = pl.dev + s.off;
   switch (s.kind) {
-    case K_SMOOTH: return BatchLaunch<T>::smooth((const BSmoothStage<T> *)tab, s.p, s.grid, s.shmem, st);
+    case K_SMOOTH: return BatchLaunch<T>::smooth((const BSmoothStage<T> *)tab, s.p, s.one != 0, s.grid, s.shmem, st);
     case K_APPLY:
       return BatchLaunch<T>::apply((const BApplyStage<T> *)tab, s.p, s.tile, s.resid, s.grid, s.shmem, st);
     case K_PASS: return BatchLaunch<T>::pass((const BPassStage<T> *)tab, s.grid, st);
