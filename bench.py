@@ -650,13 +650,13 @@ def main():
         roof = {"bound": "alu", "achieved": round(sm["achieved_tflops"], 2), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(sm["achieved_tflops"] / FP64_PEAK_TFLOPS, 4)}
     # the library's choice for these launches: FP32 colors of 3D Q4 with at least 64 patches per
-    # CU run one wave per patch, FP64 colors two
+    # CU run one wave per patch (half the per-degree lanes), FP64 colors two
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     smallest_color = min((n - 1 - f) // 2 + 1 for f in (1, 2)) ** dim
     wave32 = dim == 3 and p == 4 and smallest_color >= 64 * ncu
     roof.update({"traffic": measured_traffic("k_smooth_fp64_q4_64cube"),
                  "kernel": f"k_smooth<3,double,4,{{1,3,4}},ONE> (finest level {n}^3, one color launch)",
-                 "fp32_kernel": ("k_smooth_1w<3,float,4,{1,3,4}> (one wave per patch)" if wave32
+                 "fp32_kernel": ("k_smooth_h<3,float,4,{1,3,4},64> (one wave per patch)" if wave32
                                  else "k_smooth<3,float,4,{1,3,4},ONE>"),
                  "avg_launch_us": round(sm["avg_launch_us"], 2), "bytes_per_launch": sm["bytes_per_launch"],
                  "flops_per_launch": sm["flops_per_launch"], "flop_per_byte": round(sm["flop_per_byte"], 2),

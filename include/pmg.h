@@ -75,13 +75,13 @@ enum { PMG_SMOOTHER_JACOBI = 0, PMG_SMOOTHER_REINFORCED = 1 };
 
 /* Lanes per patch of the Cartesian smoother launches: by launch size (a color with at
  * most 4 patches per compute unit runs 256 lanes per patch, larger colors the per-degree
- * count: 64 for p <= 3, 128 for p = 4, 256 or 512 above; in 3D at p = 4 an FP32 color with
- * at least 64 patches per compute unit runs one wave of 64 lanes per patch when the local
- * solver is the default one half V-cycle), or always one of them: NARROW the per-degree
- * count, WIDE 256, WAVE one wave where the degree has a one-wave kernel (3D p = 4 with the
- * default local solver; elsewhere the per-degree count).  The arithmetic is the same; the
- * choice only trades latency against occupancy. */
-enum { PMG_LANES_AUTO = 0, PMG_LANES_NARROW = 1, PMG_LANES_WIDE = 2, PMG_LANES_WAVE = 3 };
+ * count: 64 for p <= 3, 128 for p = 4, 256 or 512 above; in 3D at p = 4 and 5 an FP32 color
+ * with at least 64 patches per compute unit runs half the per-degree count, 64 and 128
+ * lanes, when the local solver is the default one half V-cycle), or always one of them:
+ * NARROW the per-degree count, WIDE 256, HALF half the per-degree count where the degree has
+ * that kernel (3D p = 4, 5 with the default local solver; elsewhere the per-degree count).
+ * The arithmetic is the same; the choice only trades latency against occupancy. */
+enum { PMG_LANES_AUTO = 0, PMG_LANES_NARROW = 1, PMG_LANES_WIDE = 2, PMG_LANES_HALF = 3 };
 
 typedef struct {
   int local_solver; /* PMG_LOCAL_HALF_V (default), PMG_LOCAL_FULL_V or PMG_LOCAL_DIRECT */
@@ -92,7 +92,7 @@ typedef struct {
   double rtol;      /* outer stop: |b - A x|_2 <= rtol |b|_2, default 1e-8               */
   int n_omega;      /* 0: library damping; else the number of valid entries in omega     */
   double omega[8];  /* Jacobi damping per p-level, coarsest first (entry 0 is unused)    */
-  int patch_lanes;  /* PMG_LANES_AUTO (default), _NARROW, _WIDE or _WAVE                 */
+  int patch_lanes;  /* PMG_LANES_AUTO (default), _NARROW, _WIDE or _HALF                 */
   int local_smoother; /* PMG_SMOOTHER_JACOBI (default) or PMG_SMOOTHER_REINFORCED       */
 } pmg_config;
 

@@ -753,7 +753,7 @@ int pmg_setup_dofmap(const pmg_mesh *m, int degree, const int32_t *p_levels, int
   if (!(c.rtol > 0.0) || !(c.rtol < 1.0)) return fail(PMG_ERR_INVALID_ARG, "rtol must be in (0, 1)");
   if (c.n_omega < 0 || c.n_omega > (int)deg.size()) return fail(PMG_ERR_INVALID_ARG, "n_omega out of range");
   if (c.patch_lanes != PMG_LANES_AUTO && c.patch_lanes != PMG_LANES_NARROW && c.patch_lanes != PMG_LANES_WIDE &&
-      c.patch_lanes != PMG_LANES_WAVE)
+      c.patch_lanes != PMG_LANES_HALF)
     return fail(PMG_ERR_INVALID_ARG, "patch_lanes unknown");
   for (int i = 1; i < c.n_omega; ++i)
     if (!(c.omega[i] > 0.0 && c.omega[i] < 2.0)) return fail(PMG_ERR_INVALID_ARG, "omega[%d] must be in (0, 2)", i);

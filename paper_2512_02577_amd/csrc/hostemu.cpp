@@ -11,8 +11,8 @@
 //
 // Lane codes of the entry points: 0 = one lane; 1 = the lane count of the library's
 // launch of that body (patch_threads, apply_threads, ...); 2 = 256 lanes (the latency
-// variant of the patch smoother); 3 = one wave of 64 lanes (the patch smoother's one-wave
-// kernel of large launches).  Table modes: 0 = every 1D table in its own exactly sized
+// variant of the patch smoother); 3 = half the library's count (the patch smoother's kernel
+// of large launches at 3D degrees 4 and 5).  Table modes: 0 = every 1D table in its own exactly sized
 // vector; 1 = the library's concatenated table block (tab_layout.h).
 #include <pthread.h>
 
@@ -184,8 +184,12 @@ struct EmuSmooth {
                          : go<patch_threads(P, DIM), false>(base, n, color_dir, local_only, n_blocks);
         case 2: return o ? go<256, true>(base, n, color_dir, local_only, n_blocks)
                          : go<256, false>(base, n, color_dir, local_only, n_blocks);
-        case 3: return o ? go<64, true>(base, n, color_dir, local_only, n_blocks)
-                         : go<64, false>(base, n, color_dir, local_only, n_blocks);
+        case 3:
+          if constexpr (DIM == 3 && (P == 4 || P == 5))
+            return o ? go<patch_threads(P, DIM) / 2, true>(base, n, color_dir, local_only, n_blocks)
+                     : go<patch_threads(P, DIM) / 2, false>(base, n, color_dir, local_only, n_blocks);
+          else
+            return -1;
         default: return -1;
       }
     }

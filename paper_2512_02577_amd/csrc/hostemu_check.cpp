@@ -103,11 +103,11 @@ int main(int argc, char **argv) {
             check(pmgemu_smooth(dim, n, p, deg.data(), L, om.data(), 2, 0, 1, 1, u.data(), b.data(), lanes, 0, 1),
                   "smooth direct", dim, p, n, lanes);
           }
-          if (dim == 3 && p == 4)  // the one-wave kernel of large launches (default solver only)
+          if (dim == 3 && (p == 4 || p == 5))  // the half-lane kernel of large launches (default solver)
             for (int tabmode = 0; tabmode < 2; ++tabmode)
               check(pmgemu_smooth(dim, n, p, deg.data(), L, om.data(), 0, 0, 1, tabmode ? 1 : -1, u.data(), b.data(), 3,
                                   1, tabmode),
-                    "smooth one wave", dim, p, n, 3);
+                    "smooth half lanes", dim, p, n, 3);
           const long nd = ipow(2 * p - 1, dim), np = ipow(n - 1, dim);
           auto r = rnd(nd * np, 3);
           std::vector<double> d(nd * np);

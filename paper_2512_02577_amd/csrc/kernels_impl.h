@@ -38,11 +38,11 @@ __global__ __launch_bounds__(256) void k_smooth_w(SmoothArgs<T> a) {
   B::template smooth_patch<ONE>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
-// One wave per patch, for the largest launches of the default local solver where the
-// per-degree count is two waves (3D degree 4).
-template <int DIM, typename T, int P, class H>
-__global__ __launch_bounds__(64) void k_smooth_1w(SmoothArgs<T> a) {
-  using B = PatchBody<DIM, T, 64, P, H>;
+// Half the per-degree lanes per patch (NT: one wave at 3D degree 4, two at degree 5), for the
+// largest launches of the default local solver.
+template <int DIM, typename T, int P, class H, int NT>
+__global__ __launch_bounds__(NT) void k_smooth_h(SmoothArgs<T> a) {
+  using B = PatchBody<DIM, T, NT, P, H>;
   B::template smooth_patch<true>(threadIdx.x, blockIdx.x, lds_arena<T>(), a);
 }
 
@@ -147,14 +147,16 @@ struct SmoothL {
         using B = PatchBody<DIM, T, patch_threads(P, DIM, sizeof(T)), P, H>;
         const bool one = a.full == 0 && a.n_iter == 1 && a.direct == 0 && a.reinf == 0;
         const size_t bytes = (one ? B::arena_one() : B::arena(a.n_iter)) * sizeof(T);
-        // patch_lanes: 0 by launch size, 1 always the per-degree count, 2 always 256, 3 one
-        // wave where the degree has a one-wave variant (else the per-degree count)
+        // patch_lanes: 0 by launch size, 1 always the per-degree count, 2 always 256, 3 half the
+        // per-degree count where the degree has that variant (else the per-degree count)
         const bool wide = ar.patch_lanes == 2 || (ar.patch_lanes == 0 && a.n_patch <= kWideLaunch * ar.ncu);
-        if constexpr (DIM == 3 && patch_threads(P, DIM, sizeof(T)) == 128) {
-          const bool wave =
-              ar.patch_lanes == 3 || (ar.patch_lanes == 0 && sizeof(T) == 4 && a.n_patch >= kWaveLaunch * ar.ncu);
-          if (one && wave && bytes <= ar.lds_max)
-            return launch_arena(k_smooth_1w<DIM, T, P, H>, k_smooth_g<DIM, T, P, H>, a.n_patch, 64, bytes, ar, s, a);
+        constexpr int PT = patch_threads(P, DIM, sizeof(T));
+        if constexpr (DIM == 3 && (P == 4 || P == 5) && PT >= 128) {
+          const bool half =
+              ar.patch_lanes == 3 || (ar.patch_lanes == 0 && sizeof(T) == 4 && a.n_patch >= kHalfLaunch * ar.ncu);
+          if (one && half && bytes <= ar.lds_max)
+            return launch_arena(k_smooth_h<DIM, T, P, H, PT / 2>, k_smooth_g<DIM, T, P, H>, a.n_patch, PT / 2, bytes,
+                                ar, s, a);
         }
         if constexpr (patch_threads(P, DIM, sizeof(T)) < 256)
           if (wide && bytes <= ar.lds_max)

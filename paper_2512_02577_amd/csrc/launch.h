@@ -23,13 +23,15 @@ struct Arena {
 // (unless the problem's configuration fixes the lane count).
 constexpr int kWideLaunch = 4;
 
-// FP32 launches of the 3D degree-4 default-solver kernel with at least this many patches per
-// CU run one wave per patch (unless the configuration fixes the lane count): the FP32 arena
-// lets 24 patches share a CU, which two waves per patch would cap at 16 (32 waves per CU),
-// and fewer lanes per patch leave fewer of them idle in the short contraction stages.
-// Smaller launches keep two waves per patch, which finish each patch sooner; FP64 patches
-// (12 per CU by LDS whatever their lane count) measured the same either way and keep two.
-constexpr int kWaveLaunch = 64;
+// FP32 launches of the 3D degree-4 and degree-5 default-solver kernels with at least this many
+// patches per CU run half the per-degree lanes per patch (one wave at degree 4, two at degree
+// 5; unless the configuration fixes the lane count): their FP32 arenas let 27 and 14 patches
+// share a CU, which the per-degree count (two and four waves) would cap at 16 and 8 (32 waves
+// per CU), and fewer lanes per patch leave fewer of them idle in the short contraction
+// stages.  Smaller launches keep the per-degree count, which finishes each patch sooner; FP64
+// patches (13 and 7 per CU by LDS whatever their lane count) measured the same or slower with
+// fewer lanes and keep it.
+constexpr int kHalfLaunch = 64;
 
 // Bytes of LDS a workgroup may use on the current device (queried once per process).
 inline size_t device_lds_limit() {

@@ -22,7 +22,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CON
 FP64, FP32, FP32_BF16 = 0, 1, 2
 LOCAL_HALF_V, LOCAL_FULL_V, LOCAL_DIRECT = 0, 1, 2
 SMOOTHER_JACOBI, SMOOTHER_REINFORCED = 0, 1
-LANES_AUTO, LANES_NARROW, LANES_WIDE, LANES_WAVE = 0, 1, 2, 3
+LANES_AUTO, LANES_NARROW, LANES_WIDE, LANES_HALF = 0, 1, 2, 3
 
 
 class PmgError(RuntimeError):

@@ -5,13 +5,14 @@ the FP64 oracle per degree.
 A color launch runs the per-degree lane count (64 lanes for p <= 3, 128 for p = 4, 256
 or 512 above) or the 256-lane latency variant, each either in the variant compiled for the
 default local solver (one half V-cycle, one Richardson step) or in the general one; 3D
-degree-4 FP32 colors of at least 64 patches per CU run the default solver on one wave per
-patch (the configuration can force that kernel in both precisions).
-Large problems take the per-degree width (or the one-wave kernel), small ones the latency
+degree-4 and degree-5 FP32 colors of at least 64 patches per CU run the default solver on
+half the per-degree lanes (the configuration can force that kernel in both precisions).
+Large problems take the per-degree width (or the half-lane kernel), small ones the latency
 variant; the configuration fixes one of them here so that small meshes the oracle finishes
 in seconds reach each, and one natural case has more than 1,024 patches per color (the
-per-degree width at full size).  At 64^3 Q4 the one-wave kernel that the benchmark's
-finest level runs is compared with the per-degree width on the same inputs.
+per-degree width at full size).  At 64^3 Q4 and Q5 the half-lane kernel that the
+benchmark's finest levels run in FP32 is compared with the per-degree width on the same
+inputs.
 
 Tolerances as in test_gpu_parity.py: FP64 smoother / V-cycle 1e-11, FP32 2e-4 (max-norm
 relative to the oracle's result).
@@ -72,9 +73,9 @@ WIDTH_CASES = [(3, 5, 1, None), (3, 5, 2, None), (3, 4, 3, None), (3, 4, 4, None
 SOLVERS = [("half", 1), ("full", 1), ("half", 2)]  # the first is the default solver's own variant
 
 
-# the one-wave kernel exists for 3D degree 4 only (elsewhere LANES_WAVE is the per-degree count)
+# the half-lane kernel exists for 3D degrees 4 and 5 (elsewhere LANES_HALF is the per-degree count)
 WIDTH_PARAMS = [(c, lanes) for c in WIDTH_CASES for lanes in (pmg.LANES_NARROW, pmg.LANES_WIDE)] + \
-    [(c, pmg.LANES_WAVE) for c in WIDTH_CASES if c[0] == 3 and c[2] == 4]
+    [(c, pmg.LANES_HALF) for c in WIDTH_CASES if c[0] == 3 and c[2] == 4]
 
 
 @pytest.mark.parametrize("case,lanes", WIDTH_PARAMS)
@@ -96,7 +97,7 @@ def test_smoother_widths_fp64(case, lanes):
 
 
 @pytest.mark.parametrize("dim,n,p,lanes", [(d, n, p, l) for (d, n, p) in [(3, 5, 2), (3, 4, 4), (2, 7, 3)]
-                                             for l in (pmg.LANES_NARROW, pmg.LANES_WIDE)] + [(3, 4, 4, pmg.LANES_WAVE)])
+                                             for l in (pmg.LANES_NARROW, pmg.LANES_WIDE)] + [(3, 4, 4, pmg.LANES_HALF)])
 def test_smoother_widths_fp32(dim, n, p, lanes):
     print(f"case smoother widths fp32 dim {dim} n {n} p {p} lanes {lanes}", flush=True)
     deg = p_hierarchy(p)
@@ -142,25 +143,26 @@ def test_smoother_natural_full_width_launch(name, p, direction, seeds):
     assert sampled_relerr(host(ud), ref) <= 1e-11
 
 
-def test_one_wave_kernel_at_the_benchmark_size():
-    # 64^3 cells, Q4 (16,974,593 nodes): every color has more than 64 patches per CU, so the
-    # default configuration runs the one-wave kernel in FP32 (forced here for FP64 too); the
-    # per-degree width (compared with the oracle above and at 24^3) on the same inputs must
-    # give the same sweep up to the rounding of the coarsest p-level's block sum, in both
-    # directions and both precisions
-    dim, n, p = 3, 64, 4
-    print("case one-wave kernel 64^3 Q4 against the per-degree width", flush=True)
-    auto, narrow = make(dim, n, p, lanes=pmg.LANES_WAVE), make(dim, n, p, lanes=pmg.LANES_NARROW)
+@pytest.mark.parametrize("p", [4, 5])
+def test_half_lane_kernel_at_the_benchmark_size(p):
+    # 64^3 cells, Q4 / Q5 (17.0M / 33.1M nodes): every color has more than 64 patches per CU, so
+    # the default configuration runs the half-lane kernel in FP32 (forced here for FP64 too);
+    # the per-degree width (compared with the oracle above, at 24^3 and at Q5 below) on the same
+    # inputs must give the same sweep up to the rounding of the coarsest p-level's block sum, in
+    # both directions and both precisions
+    dim, n = 3, 64
+    print(f"case half-lane kernel 64^3 Q{p} against the per-degree width", flush=True)
+    half, narrow = make(dim, n, p, lanes=pmg.LANES_HALF), make(dim, n, p, lanes=pmg.LANES_NARROW)
     b = rhs_vector(dim, n, p, 53)
     u0 = np.random.default_rng(54).uniform(-1, 1, len(b))
     for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
         bd = dev(b, dtype)
         for direction in (1, -1):
-            ua, un = dev(u0, dtype), dev(u0, dtype)
-            pmg.smooth(auto, auto.finest, ua, bd, direction)
+            uh, un = dev(u0, dtype), dev(u0, dtype)
+            pmg.smooth(half, half.finest, uh, bd, direction)
             pmg.smooth(narrow, narrow.finest, un, bd, direction)
-            assert relerr(host(ua), host(un)) <= tol, (dtype, direction)
-            assert relerr(host(ua), u0) > 1e-3  # the sweep changed the iterate
+            assert relerr(host(uh), host(un)) <= tol, (dtype, direction)
+            assert relerr(host(uh), u0) > 1e-3  # the sweep changed the iterate
 
 
 @pytest.mark.parametrize("p", [5, 7])
@@ -171,7 +173,7 @@ def test_smoother_high_degree_3d(p):
     u0 = np.random.default_rng(48).uniform(-1, 1, len(b))
     for direction, tag in ((1, "asc"), (-1, "desc")):
         ref = golden(f"smooth_3d_n3_p{p}_{tag}")
-        for lanes in (pmg.LANES_AUTO, pmg.LANES_NARROW):
+        for lanes in (pmg.LANES_AUTO, pmg.LANES_NARROW) + ((pmg.LANES_HALF,) if p == 5 else ()):
             pr = make(dim, n, p, omega=list(ref["omega"]), lanes=lanes)
             ud = dev(u0)
             pmg.smooth(pr, pr.finest, ud, dev(b), direction)

@@ -141,7 +141,7 @@ def test_cell_counts_per_direction_and_lane_option():
         pmg.setup_mesh(3, (8, 1, 8))
     assert e.value.status == pmg.ERR_INVALID_ARG
     assert pmg.lib().pmg_setup_mesh(3, None, 0, None, ctypes.byref(ctypes.c_void_p())) == pmg.ERR_INVALID_ARG
-    for lanes in (pmg.LANES_AUTO, pmg.LANES_NARROW, pmg.LANES_WIDE, pmg.LANES_WAVE):
+    for lanes in (pmg.LANES_AUTO, pmg.LANES_NARROW, pmg.LANES_WIDE, pmg.LANES_HALF):
         cfg = pmg.default_config()
         cfg.patch_lanes = lanes
         pmg.setup_dofmap(pmg.setup_mesh(3, 4), 4, None, cfg)

@@ -117,8 +117,8 @@ def test_smoother_lane_teams(emu, dim, n, p, lv):
     u0 = np.random.default_rng(4).uniform(-1, 1, len(b))
     for direction in (1, -1):
         ref = ls.smooth(u0, b, descending=direction < 0)
-        # 3D degree 4 also on one wave (the one-wave kernel of large launches, default solver)
-        wave = ((3, 1, 1),) if dim == 3 and p == 4 else ()
+        # 3D degrees 4 and 5 also on half the lanes (the kernel of large launches, default solver)
+        wave = ((3, 1, 1),) if dim == 3 and p in (4, 5) else ()
         for lanes, one, tabmode in ((1, 1, 1), (2, 1, 0), (1, 0, 0), (2, 0, 1)) + wave:
             u = u0.copy()
             assert emu.pmgemu_smooth(dim, n, p, ci(deg), len(deg), cd(om), 0, 0, 1, direction, P(u), P(b), lanes,
